@@ -1,0 +1,619 @@
+/*
+ * srm_oracle.c -- plain sequential CPU oracle of the Swelling and Random
+ * Migration (SRM) sweep.  TEST INFRASTRUCTURE ONLY: it is the reference the
+ * GPU library is checked against and is never called by the library.
+ *
+ * It follows the paper's Algorithms 1-6 (Section 2) step by step, with the
+ * readings listed below.  Positions are stored in particle-id order,
+ * array-of-structures pos[3*i + a] (the paper's particle set P with
+ * positions r_i); cell lists are Alg. 2's per-cell particle lists, filled in
+ * ascending id.
+ *
+ * Floating point: IEEE binary64, round to nearest, built with
+ * -ffp-contract=off -fno-fast-math on x86-64 (SSE2, no x87), so every
+ * expression below is evaluated exactly as written, left to right.
+ *
+ * Readings of the paper (where it is silent or ambiguous):
+ *  - swelling (Sec. 2 step a, Alg. 1 step "scale all particles"): additive in
+ *    the radius scale s: s' = min(s + c_w * s_target, s_target); R_i = s*rho_i.
+ *    The clamp at s_target is the final "minor adjustment" of Sec. 2.
+ *  - cell size (Alg. 1): cs = 2.5 * max R' + 2.5 * c_m with the post-swell
+ *    radii; per axis m = floor(L/cs) capped at ncap (largest even m with
+ *    m^d <= N); the axis is split into N_a = m - (m mod 2) equal cells when
+ *    m >= 4, else into one cell.  Even N_a >= 4 makes the 2^d parity colouring
+ *    below valid under periodic wrap.
+ *  - binning (Alg. 2): c_a = (int)(x_a * (N_a / L_a)), and c_a == N_a -> 0.
+ *  - processing order (Alg. 3 "for each particle"): colour phases
+ *    g = sum_a (c_a & 1) << a (axes with one cell contribute 0), g ascending;
+ *    within a phase cells by ascending linear index c = cx + Nx*(cy + Ny*cz);
+ *    within a cell ascending particle id.  Cells of one colour never share a
+ *    3^d neighbourhood, so any order of them gives the same result.
+ *  - collision test (Alg. 5): cell of the tested position, 3^d neighbour
+ *    cells of the current lists, the particle itself excluded, minimum image
+ *    per axis, squared form q <= (R_i + R_j)^2 (touching counts as overlap).
+ *  - unit random vector (Alg. 3): Philox4x64-10 counter-based draws,
+ *    rejection sampling in [-1,1)^d, normalised (no trigonometry); counter
+ *    (id, sweep, kind<<48 | k<<32 | l<<16 | round, stream), key (seed, 0).
+ *  - shake (Sec. 2 step d, Alg. 1 else-branch): N_k passes over P at P's
+ *    radii, re-binning before each pass; s unchanged.
+ *  - the sweep counter t advances after every sweep, committed or shaken.
+ *  - termination (Sec. 2 step e): s == s_target after a committed sweep.
+ *  - thin platelets (Sec. 3.3): zero-thickness disks with a unit normal;
+ *    exact disk-disk intersection (chords on the planes' common line); the
+ *    centre trial and a normal trial (stream 1, step c_n) are accepted or
+ *    rejected together.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define O_OK 0
+#define O_EINVAL (-1)
+#define O_ENOMEM (-2)
+#define O_EOVERLAP (-4)
+#define O_ENOTCONV (-5)
+
+#define O_BALL 0
+#define O_PLATELET 1
+
+#define O_MAIN 0
+#define O_SHAKE 1
+
+typedef struct {
+    int32_t dim, shape;
+    int64_t n;
+    double box[3];
+    double s_target, c_w, c_m, c_n, thick_ratio;
+    int32_t n_k, n_l;
+    uint64_t seed;
+} o_params;
+
+typedef struct {
+    o_params p;
+    double *pos;       /* [3n], id order; z unused in 2D */
+    double *nrm;       /* [3n] unit normals (platelets) or NULL */
+    const double *rho; /* [n] shape radii or NULL (all 1) */
+    double s;          /* current radius scale */
+    int64_t t;         /* sweep counter */
+} o_state;
+
+typedef struct {
+    int32_t committed, passes_main, passes_shake, pad;
+    int64_t na[3];
+    double s_new;
+    int64_t n_failed_last;
+} o_sweep_info;
+
+typedef struct {
+    int64_t na[3];
+    double inv_w[3];
+    int64_t ncell;
+    int64_t *cell;   /* [n] linear cell of each particle */
+    int64_t *start;  /* [ncell+1] */
+    int64_t *member; /* [n] particle ids grouped by cell, ascending id */
+} o_cells;
+
+/* ------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).                  */
+/* ------------------------------------------------------------------ */
+void o_philox(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        unsigned __int128 p0 = (unsigned __int128)M0 * x0;
+        unsigned __int128 p1 = (unsigned __int128)M1 * x2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        uint64_t y0 = hi1 ^ x1 ^ k0;
+        uint64_t y1 = lo1;
+        uint64_t y2 = hi0 ^ x3 ^ k1;
+        uint64_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Unit random vector times `len` (Alg. 3, "c_m * Unit Random Vector").
+ * Returns the number of Philox rounds used (65 = fallback). */
+int o_unitvec(int dim, uint64_t seed, uint64_t id, uint64_t t, uint32_t kind,
+              uint32_t k, uint32_t l, uint64_t stream, double len, double v[3])
+{
+    const uint64_t key[2] = {seed, 0};
+    for (uint32_t r = 0; r < 64; ++r) {
+        uint64_t ctr[4], W[4];
+        ctr[0] = id;
+        ctr[1] = t;
+        ctr[2] = ((uint64_t)kind << 48) | ((uint64_t)k << 32) | ((uint64_t)l << 16) | (uint64_t)r;
+        ctr[3] = stream;
+        o_philox(ctr, key, W);
+        double w[3];
+        for (int a = 0; a < 3; ++a) {
+            double u = (double)(W[a] >> 11) * 0x1p-53;
+            w[a] = 2.0 * u - 1.0;
+        }
+        double q = w[0] * w[0] + w[1] * w[1];
+        if (dim == 3) q = q + w[2] * w[2];
+        if (q > 0.0 && q <= 1.0) {
+            double g = len / sqrt(q);
+            v[0] = w[0] * g;
+            v[1] = w[1] * g;
+            v[2] = (dim == 3) ? w[2] * g : 0.0;
+            return (int)r + 1;
+        }
+    }
+    v[0] = len; v[1] = 0.0; v[2] = 0.0;
+    return 65;
+}
+
+/* Alg. 4: periodic wrapping of one coordinate. */
+static double o_wrap(double x, double L)
+{
+    if (x < 0.0) x += L;
+    if (x >= L) x -= L;
+    return x;
+}
+
+/* Minimum-image convention of Alg. 5 for one axis. */
+static double o_minimg(double d, double L)
+{
+    if (d > 0.5 * L) d -= L;
+    if (d < -0.5 * L) d += L;
+    return d;
+}
+
+static double o_radius(const o_state *st, double s, int64_t i)
+{
+    return st->rho ? s * st->rho[i] : s * 1.0;
+}
+
+/* Zero-thickness disk-disk intersection.  Disk 1 = (c1, n1, a1), disk 2 =
+ * (c2, n2, a2); callers pass the lower particle id as disk 1. */
+int o_disks_intersect(const double c1[3], const double n1[3], double a1,
+                      const double c2[3], const double n2[3], double a2,
+                      const double box[3])
+{
+    double dx = o_minimg(c2[0] - c1[0], box[0]);
+    double dy = o_minimg(c2[1] - c1[1], box[1]);
+    double dz = o_minimg(c2[2] - c1[2], box[2]);
+    double dd = dx * dx + dy * dy + dz * dz;
+    double sa = a1 + a2;
+    if (dd > sa * sa) return 0;
+    /* u = n1 x n2: direction of the planes' common line */
+    double ux = n1[1] * n2[2] - n1[2] * n2[1];
+    double uy = n1[2] * n2[0] - n1[0] * n2[2];
+    double uz = n1[0] * n2[1] - n1[1] * n2[0];
+    double uu = ux * ux + uy * uy + uz * uz;
+    if (uu == 0.0) {
+        /* parallel planes: intersect only when coplanar (circle test) */
+        double hn = n1[0] * dx + n1[1] * dy + n1[2] * dz;
+        return hn == 0.0;
+    }
+    /* foot p of centre 1 on the common line: p = (u x n1) * (h / uu) */
+    double h = n2[0] * dx + n2[1] * dy + n2[2] * dz;
+    double wx = uy * n1[2] - uz * n1[1];
+    double wy = uz * n1[0] - ux * n1[2];
+    double wz = ux * n1[1] - uy * n1[0];
+    double f = h / uu;
+    double px = wx * f, py = wy * f, pz = wz * f;
+    double A = a1 * a1 - (px * px + py * py + pz * pz);
+    if (A < 0.0) return 0;
+    /* foot of centre 2: p + t0 u */
+    double ex = dx - px, ey = dy - py, ez = dz - pz;
+    double t0 = (ex * ux + ey * uy + ez * uz) / uu;
+    double B = a2 * a2 - ((ex * ex + ey * ey + ez * ez) - (t0 * t0) * uu);
+    if (B < 0.0) return 0;
+    /* chords [-sqrt(A/uu), sqrt(A/uu)] and t0 +- sqrt(B/uu) overlap */
+    double Ap = A / uu, Bp = B / uu, C = t0 * t0;
+    double D = (C - Ap) - Bp;
+    if (D <= 0.0) return 1;
+    return D * D <= (4.0 * Ap) * Bp;
+}
+
+/* ------------------------------------------------------------------ */
+/* Cells (Alg. 1 cell size, Alg. 2 build cell list).                   */
+/* ------------------------------------------------------------------ */
+static int64_t o_ncap(int dim, int64_t n)
+{
+    int64_t m = 0;
+    for (;;) {
+        int64_t c = m + 2, pw = 1;
+        for (int a = 0; a < dim; ++a) pw *= c;
+        if (pw > n) break;
+        m = c;
+    }
+    return m;
+}
+
+void o_grid(const o_params *p, double rmax, int64_t na[3], double inv_w[3])
+{
+    double cs = 2.5 * rmax + 2.5 * p->c_m;
+    int64_t ncap = o_ncap(p->dim, p->n);
+    for (int a = 0; a < 3; ++a) {
+        if (a >= p->dim) { na[a] = 1; inv_w[a] = 1.0 / p->box[a]; continue; }
+        int64_t m;
+        double q = (cs > 0.0) ? p->box[a] / cs : 0.0;
+        if (!(cs > 0.0) || q >= (double)ncap) m = ncap;
+        else m = (int64_t)q;
+        na[a] = (m >= 4) ? m - (m & 1) : 1;
+        inv_w[a] = (double)na[a] / p->box[a];
+    }
+}
+
+static void o_cell_coords(const o_cells *g, const double x[3], int dim, int64_t c[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        if (a >= dim) { c[a] = 0; continue; }
+        int64_t ca = (int64_t)(x[a] * g->inv_w[a]);
+        if (ca == g->na[a]) ca = 0;
+        c[a] = ca;
+    }
+}
+
+static int64_t o_linear(const o_cells *g, const int64_t c[3])
+{
+    return c[0] + g->na[0] * (c[1] + g->na[1] * c[2]);
+}
+
+static void o_cells_free(o_cells *g)
+{
+    free(g->cell); free(g->start); free(g->member);
+    g->cell = g->start = g->member = NULL;
+}
+
+static int o_cells_build(o_cells *g, const o_params *p, const int64_t na[3],
+                         const double inv_w[3], const double *pos)
+{
+    int64_t n = p->n;
+    for (int a = 0; a < 3; ++a) { g->na[a] = na[a]; g->inv_w[a] = inv_w[a]; }
+    g->ncell = na[0] * na[1] * na[2];
+    g->cell = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    g->start = (int64_t *)calloc((size_t)g->ncell + 1, sizeof(int64_t));
+    g->member = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!g->cell || !g->start || !g->member) { o_cells_free(g); return O_ENOMEM; }
+    /* Alg. 2: for each particle q (ascending id): cells[c].Add(q) */
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c[3];
+        o_cell_coords(g, &pos[3 * i], p->dim, c);
+        g->cell[i] = o_linear(g, c);
+        g->start[g->cell[i] + 1] += 1;
+    }
+    for (int64_t c = 0; c < g->ncell; ++c) g->start[c + 1] += g->start[c];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(g->ncell > 0 ? g->ncell : 1));
+    if (!fill) { o_cells_free(g); return O_ENOMEM; }
+    memcpy(fill, g->start, sizeof(int64_t) * (size_t)g->ncell);
+    for (int64_t i = 0; i < n; ++i) g->member[fill[g->cell[i]]++] = i;
+    free(fill);
+    return O_OK;
+}
+
+/* Cell assignment only (Alg. 2 lines computing c_x, c_y[, c_z]). */
+int o_bin(const o_params *p, const int64_t na[3], const double inv_w[3],
+          const double *pos, int64_t *cell_out)
+{
+    o_cells g;
+    for (int a = 0; a < 3; ++a) { g.na[a] = na[a]; g.inv_w[a] = inv_w[a]; }
+    for (int64_t i = 0; i < p->n; ++i) {
+        int64_t c[3];
+        o_cell_coords(&g, &pos[3 * i], p->dim, c);
+        cell_out[i] = o_linear(&g, c);
+    }
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Alg. 5: collision check for particle i tested at position y.        */
+/* ------------------------------------------------------------------ */
+static int o_collides(const o_state *st, const o_cells *g, int64_t i,
+                      const double y[3], const double ny[3], double s)
+{
+    const o_params *p = &st->p;
+    int64_t c[3];
+    o_cell_coords(g, y, p->dim, c);
+    double Ri = o_radius(st, s, i);
+    int64_t lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        if (g->na[a] >= 3) { lo[a] = -1; hi[a] = 1; }
+        else { lo[a] = 0; hi[a] = 0; }
+    }
+    for (int64_t sz = lo[2]; sz <= hi[2]; ++sz)
+    for (int64_t sy = lo[1]; sy <= hi[1]; ++sy)
+    for (int64_t sx = lo[0]; sx <= hi[0]; ++sx) {
+        int64_t nc[3];
+        nc[0] = (c[0] + sx + g->na[0]) % g->na[0];
+        nc[1] = (c[1] + sy + g->na[1]) % g->na[1];
+        nc[2] = (c[2] + sz + g->na[2]) % g->na[2];
+        int64_t cl = o_linear(g, nc);
+        for (int64_t m = g->start[cl]; m < g->start[cl + 1]; ++m) {
+            int64_t j = g->member[m];
+            if (j == i) continue;
+            const double *xj = &st->pos[3 * j];
+            double Rj = o_radius(st, s, j);
+            if (p->shape == O_PLATELET) {
+                int hit = (i < j)
+                    ? o_disks_intersect(y, ny, Ri, xj, &st->nrm[3 * j], Rj, p->box)
+                    : o_disks_intersect(xj, &st->nrm[3 * j], Rj, y, ny, Ri, p->box);
+                if (hit) return 1;
+                continue;
+            }
+            double d0 = o_minimg(y[0] - xj[0], p->box[0]);
+            double d1 = o_minimg(y[1] - xj[1], p->box[1]);
+            double q = d0 * d0 + d1 * d1;
+            if (p->dim == 3) {
+                double d2 = o_minimg(y[2] - xj[2], p->box[2]);
+                q = q + d2 * d2;
+            }
+            double sig = Ri + Rj;
+            if (q <= sig * sig) return 1;
+        }
+    }
+    return 0;
+}
+
+/* Alg. 6: is there any colliding particle (lists from the last binning). */
+static int o_any_collision(const o_state *st, const o_cells *g, double s)
+{
+    for (int64_t i = 0; i < st->p.n; ++i) {
+        const double *nyi = st->nrm ? &st->nrm[3 * i] : NULL;
+        if (o_collides(st, g, i, &st->pos[3 * i], nyi, s)) return 1;
+    }
+    return 0;
+}
+
+static int o_colour_of(const o_cells *g, int64_t cl, int dim)
+{
+    int64_t c0 = cl % g->na[0];
+    int64_t c1 = (cl / g->na[0]) % g->na[1];
+    int64_t c2 = cl / (g->na[0] * g->na[1]);
+    int64_t c[3] = {c0, c1, c2};
+    int col = 0;
+    for (int a = 0; a < dim; ++a)
+        if (g->na[a] >= 4) col |= (int)(c[a] & 1) << a;
+    return col;
+}
+
+/* One trial displacement of particle i: y = wrap(old + v), and for platelets
+ * the trial normal m/|m| with m = n_old + w. */
+static void o_trial(const o_state *st, int64_t i, const double old[3], const double nold[3],
+                    uint32_t kind, uint32_t k, uint32_t l, double y[3], double ny[3])
+{
+    const o_params *p = &st->p;
+    double v[3];
+    o_unitvec(p->dim, p->seed, (uint64_t)i, (uint64_t)st->t, kind, k, l, 0, p->c_m, v);
+    for (int a = 0; a < 3; ++a) {
+        if (a < p->dim) y[a] = o_wrap(old[a] + v[a], p->box[a]);
+        else y[a] = old[a];
+    }
+    if (p->shape == O_PLATELET) {
+        double w[3];
+        o_unitvec(3, p->seed, (uint64_t)i, (uint64_t)st->t, kind, k, l, 1, p->c_n, w);
+        double m0 = nold[0] + w[0], m1 = nold[1] + w[1], m2 = nold[2] + w[2];
+        double mm = m0 * m0 + m1 * m1 + m2 * m2;
+        double inv = 1.0 / sqrt(mm);
+        ny[0] = m0 * inv; ny[1] = m1 * inv; ny[2] = m2 * inv;
+    }
+}
+
+/* Alg. 3 over the colour schedule: one migration pass.  `g` are the lists
+ * built at the start of the pass (Alg. 1 fills cells before each move).
+ * `mask` (optional, per linear cell) restricts the pass to a set of cells. */
+static void o_move(o_state *st, const o_cells *g, double s, uint32_t kind, uint32_t k,
+                   uint8_t *acc, const uint8_t *mask)
+{
+    const o_params *p = &st->p;
+    int ncol = 1 << p->dim;
+    for (int col = 0; col < ncol; ++col) {
+        for (int64_t cl = 0; cl < g->ncell; ++cl) {
+            if (o_colour_of(g, cl, p->dim) != col) continue;
+            if (mask && !mask[cl]) continue;
+            for (int64_t m = g->start[cl]; m < g->start[cl + 1]; ++m) {
+                int64_t i = g->member[m];
+                double *q = &st->pos[3 * i];
+                double *nq = st->nrm ? &st->nrm[3 * i] : NULL;
+                double old[3] = {q[0], q[1], q[2]};
+                double nold[3] = {0.0, 0.0, 0.0};
+                if (nq) { nold[0] = nq[0]; nold[1] = nq[1]; nold[2] = nq[2]; }
+                uint8_t code = 0;
+                for (int32_t l = 1; l <= p->n_l; ++l) {
+                    double y[3], ny[3] = {0.0, 0.0, 0.0};
+                    o_trial(st, i, old, nold, kind, k, (uint32_t)l, y, ny);
+                    if (!o_collides(st, g, i, y, ny, s)) {
+                        q[0] = y[0]; q[1] = y[1]; q[2] = y[2];
+                        if (nq) { nq[0] = ny[0]; nq[1] = ny[1]; nq[2] = ny[2]; }
+                        code = (uint8_t)l;
+                        break;
+                    }
+                    /* q = q_old: the stored position was never changed */
+                }
+                if (acc) acc[i] = code;
+            }
+        }
+    }
+}
+
+/* Fill cells (Alg. 2) then move (Alg. 3) once: one pass at radius scale s. */
+int o_pass(o_state *st, const int64_t na[3], const double inv_w[3], double s,
+           uint32_t kind, uint32_t k, uint8_t *acc, const uint8_t *mask, int32_t *overlap)
+{
+    o_cells g;
+    int rc = o_cells_build(&g, &st->p, na, inv_w, st->pos);
+    if (rc) return rc;
+    o_move(st, &g, s, kind, k, acc, mask);
+    if (overlap) *overlap = o_any_collision(st, &g, s);
+    o_cells_free(&g);
+    return O_OK;
+}
+
+/* Alg. 6 on a freshly built cell list. */
+int o_overlap(const o_state *st, const int64_t na[3], const double inv_w[3], double s,
+              int32_t *overlap)
+{
+    o_cells g;
+    int rc = o_cells_build(&g, &st->p, na, inv_w, st->pos);
+    if (rc) return rc;
+    *overlap = o_any_collision(st, &g, s);
+    o_cells_free(&g);
+    return O_OK;
+}
+
+double o_rho_max(const o_state *st)
+{
+    if (!st->rho) return 1.0;
+    double m = 0.0;
+    for (int64_t i = 0; i < st->p.n; ++i) if (st->rho[i] > m) m = st->rho[i];
+    return m;
+}
+
+/* Radius scale after one swelling step. */
+double o_swell(const o_params *p, double s)
+{
+    double ds = p->c_w * p->s_target;
+    double s1 = s + ds;
+    return (s1 < p->s_target) ? s1 : p->s_target;
+}
+
+/* ------------------------------------------------------------------ */
+/* Alg. 1: one iteration of the main loop (one sweep).                 */
+/* ------------------------------------------------------------------ */
+int o_sweep(o_state *st, o_sweep_info *info, uint8_t *acc_last)
+{
+    const o_params *p = &st->p;
+    int64_t n = p->n;
+    double s1 = o_swell(p, st->s);
+    int64_t na[3]; double inv_w[3];
+    o_grid(p, s1 * o_rho_max(st), na, inv_w);
+    size_t bytes = sizeof(double) * 3 * (size_t)(n > 0 ? n : 1);
+    /* Q = P */
+    double *qpos = (double *)malloc(bytes);
+    double *qnrm = st->nrm ? (double *)malloc(bytes) : NULL;
+    uint8_t *acc = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    if (!qpos || !acc || (st->nrm && !qnrm)) { free(qpos); free(qnrm); free(acc); return O_ENOMEM; }
+    memcpy(qpos, st->pos, bytes);
+    if (qnrm) memcpy(qnrm, st->nrm, bytes);
+    o_state q = *st;
+    q.pos = qpos; q.nrm = qnrm;
+    int collision = 1;
+    int32_t passes_main = 0, passes_shake = 0;
+    for (int32_t k = 1; k <= p->n_k; ++k) {
+        int32_t ov = 1;
+        int rc = o_pass(&q, na, inv_w, s1, O_MAIN, (uint32_t)k, acc, NULL, &ov);
+        if (rc) { free(qpos); free(qnrm); free(acc); return rc; }
+        passes_main++;
+        collision = ov;
+        if (!collision) break;
+    }
+    int64_t nfail = 0;
+    if (passes_main > 0) for (int64_t i = 0; i < n; ++i) nfail += (acc[i] == 0);
+    if (!collision) {
+        memcpy(st->pos, qpos, bytes);      /* P = Q */
+        if (qnrm) memcpy(st->nrm, qnrm, bytes);
+        st->s = s1;                         /* update volume fraction */
+        if (acc_last) memcpy(acc_last, acc, (size_t)n);
+    } else {
+        /* shake: N_k passes over P at P's radii, re-binned before each */
+        for (int32_t j = 1; j <= p->n_k; ++j) {
+            int rc = o_pass(st, na, inv_w, st->s, O_SHAKE, (uint32_t)j, acc, NULL, NULL);
+            if (rc) { free(qpos); free(qnrm); free(acc); return rc; }
+            passes_shake++;
+        }
+        if (acc_last) memcpy(acc_last, acc, (size_t)n);
+    }
+    st->t += 1;
+    if (info) {
+        info->committed = !collision;
+        info->passes_main = passes_main;
+        info->passes_shake = passes_shake;
+        for (int a = 0; a < 3; ++a) info->na[a] = na[a];
+        info->s_new = st->s;
+        info->n_failed_last = nfail;
+    }
+    free(qpos); free(qnrm); free(acc);
+    return O_OK;
+}
+
+/* Alg. 1 while loop: sweep until s == s_target or max_sweeps sweeps. */
+int o_run(o_state *st, int32_t max_sweeps, int64_t *sweeps_out, int64_t *passes_out)
+{
+    int64_t sweeps = 0, passes = 0;
+    while (st->s < st->p.s_target) {
+        if (sweeps >= max_sweeps) {
+            if (sweeps_out) *sweeps_out = sweeps;
+            if (passes_out) *passes_out = passes;
+            return O_ENOTCONV;
+        }
+        o_sweep_info info;
+        int rc = o_sweep(st, &info, NULL);
+        if (rc) return rc;
+        sweeps++;
+        passes += info.passes_main + info.passes_shake;
+    }
+    if (sweeps_out) *sweeps_out = sweeps;
+    if (passes_out) *passes_out = passes;
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Brute-force references (all pairs, O(N^2)).                        */
+/* ------------------------------------------------------------------ */
+static double o_pair_q(const o_state *st, int64_t i, int64_t j)
+{
+    const o_params *p = &st->p;
+    const double *xi = &st->pos[3 * i], *xj = &st->pos[3 * j];
+    double d0 = o_minimg(xi[0] - xj[0], p->box[0]);
+    double d1 = o_minimg(xi[1] - xj[1], p->box[1]);
+    double q = d0 * d0 + d1 * d1;
+    if (p->dim == 3) {
+        double d2 = o_minimg(xi[2] - xj[2], p->box[2]);
+        q = q + d2 * d2;
+    }
+    return q;
+}
+
+/* Pairs i<j whose shapes, grown by `gap` ((R_i + R_j) + gap for balls; radii
+ * a + gap/2 for platelets), overlap or touch; written sorted by (i, j).
+ * Returns the total count (which may exceed cap; only cap pairs written). */
+int64_t o_pairs_brute(const o_state *st, double s, double gap, int64_t cap, int32_t *ij)
+{
+    const o_params *p = &st->p;
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < p->n; ++i) {
+        for (int64_t j = i + 1; j < p->n; ++j) {
+            int hit;
+            if (p->shape == O_PLATELET) {
+                double ai = o_radius(st, s, i) + 0.5 * gap, aj = o_radius(st, s, j) + 0.5 * gap;
+                hit = o_disks_intersect(&st->pos[3 * i], &st->nrm[3 * i], ai,
+                                        &st->pos[3 * j], &st->nrm[3 * j], aj, p->box);
+            } else {
+                double sig = (o_radius(st, s, i) + o_radius(st, s, j)) + gap;
+                hit = o_pair_q(st, i, j) <= sig * sig;
+            }
+            if (hit) {
+                if (cnt < cap) { ij[2 * cnt] = (int32_t)i; ij[2 * cnt + 1] = (int32_t)j; }
+                cnt++;
+            }
+        }
+    }
+    return cnt;
+}
+
+/* Histogram of centre distances r_ij (i<j): bin b = (int)(r * (nbins / r_max)),
+ * counted when b < nbins. */
+int o_rdf_brute(const o_state *st, int32_t nbins, double r_max, uint64_t *counts)
+{
+    double inv = (double)nbins / r_max;
+    for (int32_t b = 0; b < nbins; ++b) counts[b] = 0;
+    for (int64_t i = 0; i < st->p.n; ++i)
+        for (int64_t j = i + 1; j < st->p.n; ++j) {
+            double r = sqrt(o_pair_q(st, i, j));
+            double x = r * inv;
+            if (x < (double)nbins) {
+                int64_t b = (int64_t)x;
+                if (b < nbins) counts[b]++;
+            }
+        }
+    return O_OK;
+}

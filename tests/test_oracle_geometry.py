@@ -1,0 +1,179 @@
+"""Pins of the oracle's pair enumeration, distance histogram and the thin
+platelet (zero-thickness disk) intersection test."""
+import math
+
+import numpy as np
+import pytest
+
+import srm_inputs
+from tests import brute
+
+
+def _state(oracle_lib, dim, n, seed, f):
+    w = srm_inputs.make("disks2d" if dim == 2 else "spheres3d", n=n, seed=seed, f_target=f)
+    o = oracle_lib.Oracle.from_workload(w)
+    o.run(2000)
+    return w, o
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_pairs_match_numpy_enumeration(oracle_lib, dim):
+    w, o = _state(oracle_lib, dim, 1500, 40 + dim, 0.35)
+    for gap in (0.0, 0.3 * o.s, 2.0 * o.s):
+        got = o.pairs_brute(gap)
+        ref = brute.overlapping_pairs(o.pos, np.full(w.n, o.s), w.box, dim, gap)
+        assert np.array_equal(got, ref)
+    assert len(o.pairs_brute(0.0)) == 0  # admissible end state
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_rdf_counts_match_numpy(oracle_lib, dim):
+    w, o = _state(oracle_lib, dim, 1200, 50 + dim, 0.3)
+    nbins, r_max = 64, 5.0 * o.s
+    got = o.rdf_brute(nbins, r_max)
+    n = w.n
+    ref = np.zeros(nbins, dtype=np.int64)
+    inv = nbins / r_max
+    for i in range(n - 1):
+        q = brute.q_to_all(o.pos[i + 1:], o.pos[i], w.box, dim)
+        x = np.sqrt(q) * inv
+        b = x[x < nbins].astype(np.int64)
+        ref += np.bincount(b, minlength=nbins)
+    assert np.array_equal(got.astype(np.int64), ref)
+    # no pair closer than a diameter in an admissible hard-sphere state
+    assert got[: int(2.0 * o.s * inv) - 1].sum() == 0
+
+
+def test_rdf_and_pairs_translation_invariant_on_dyadic_grid(oracle_lib):
+    """Positions on a 2^-30 grid, shifted by a multiple of 2^-30 with wrap:
+    differences and squared sums are exact, so counts and pair sets agree
+    bit for bit."""
+    rng = np.random.default_rng(3)
+    n, dim = 800, 3
+    pos = rng.integers(0, 2**30, size=(dim, n)).astype(np.float64) * 2.0**-30
+    s = 0.02
+    base = oracle_lib.Oracle(dim=dim, n=n, s_target=s, c_w=0.0, c_m=0.0, n_k=1, n_l=1, seed=0,
+                             pos=pos, s0=s)
+    shift = rng.integers(0, 2**30, size=(dim, 1)).astype(np.float64) * 2.0**-30
+    moved = pos + shift
+    moved[moved >= 1.0] -= 1.0
+    other = oracle_lib.Oracle(dim=dim, n=n, s_target=s, c_w=0.0, c_m=0.0, n_k=1, n_l=1, seed=0,
+                              pos=moved, s0=s)
+    assert np.array_equal(base.pairs_brute(0.01), other.pairs_brute(0.01))
+    assert np.array_equal(base.rdf_brute(32, 0.2), other.rdf_brute(32, 0.2))
+    assert len(base.pairs_brute(0.01)) > 0
+
+
+# ---------------------------------------------------------------- platelets
+
+def _rand_unit(rng):
+    v = rng.standard_normal(3)
+    return v / np.linalg.norm(v)
+
+
+def test_disks_coplanar_reduce_to_circle_test(oracle_lib):
+    """Both normals +z, centres in one plane: intersect iff |d| <= a1 + a2."""
+    for d in [0.0, 0.5, 0.999, 1.0, 1.001, 1.5]:
+        c1 = np.array([0.5, 0.5, 0.5])
+        c2 = c1 + np.array([d * 0.6, d * 0.8, 0.0]) * 0.25
+        nz = np.array([0.0, 0.0, 1.0])
+        got = oracle_lib.disks_intersect(c1, nz, 0.1, c2, nz, 0.15)
+        dist = math.hypot((c2 - c1)[0], (c2 - c1)[1])
+        assert got == (dist <= 0.25)
+    # parallel but not coplanar: never
+    c2 = np.array([0.5, 0.5, 0.5 + 1e-6])
+    assert not oracle_lib.disks_intersect(c1, nz, 0.1, c2, nz, 0.1)
+
+
+def test_disks_perpendicular_analytic(oracle_lib):
+    """Disk 1 in the plane z=0 (normal z), disk 2 in the plane x=0 (normal x)
+    through the point (0, 0, h): disk 2 meets z=0 in the chord |y - y2| <=
+    sqrt(a2^2 - h^2) on x=0; disk 1 covers |y| <= a1 there."""
+    a1, a2 = 0.1, 0.08
+    base = np.array([0.5, 0.5, 0.5])
+    for h in [0.0, 0.03, 0.079, 0.081]:
+        for y2 in [0.0, 0.1, 0.15, 0.16, 0.2]:
+            c2 = base + np.array([0.0, y2, h])
+            got = oracle_lib.disks_intersect(base, np.array([0, 0, 1.0]), a1, c2,
+                                             np.array([1.0, 0, 0]), a2)
+            if h > a2:
+                expect = False
+            else:
+                half = math.sqrt(a2 * a2 - h * h)
+                expect = abs(y2) <= a1 + half
+            margin = abs(abs(y2) - (a1 + math.sqrt(max(a2 * a2 - h * h, 0.0))))
+            if margin > 1e-9 and abs(h - a2) > 1e-9:
+                assert got == expect, (h, y2)
+
+
+def _chords_overlap_ref(c1, n1, a1, c2, n2, a2):
+    """Independent formulation: solve for a point on the planes' common line
+    with a 3x3 linear system, then compare chord intervals with sqrt in
+    long double.  Returns (answer, margin)."""
+    d = (c2 - c1).astype(np.longdouble)
+    n1l, n2l = n1.astype(np.longdouble), n2.astype(np.longdouble)
+    u = np.cross(n1l, n2l)
+    M = np.array([n1, n2, np.cross(n1, n2)], dtype=np.float64)
+    rhs = np.array([0.0, float(np.dot(n2l, d)), 0.0])
+    p = np.linalg.solve(M, rhs).astype(np.longdouble)  # on both planes, closest to c1
+    uu = np.dot(u, u)
+    e1 = p
+    A = a1 * a1 - np.dot(e1, e1)
+    t1 = np.dot(d - p, u) / uu
+    e2 = d - (p + t1 * u)
+    B = a2 * a2 - np.dot(e2, e2)
+    if A < 0 or B < 0:
+        return False, float(min(abs(A), abs(B)))
+    reach = np.sqrt(A / uu) + np.sqrt(B / uu)
+    return bool(abs(t1) <= reach), float(abs(abs(t1) - reach))
+
+
+def test_disks_random_against_independent_formulation(oracle_lib):
+    rng = np.random.default_rng(11)
+    checked = hits = 0
+    for _ in range(20000):
+        c1 = rng.uniform(0.3, 0.7, 3)
+        c2 = c1 + rng.uniform(-0.2, 0.2, 3)
+        n1, n2 = _rand_unit(rng), _rand_unit(rng)
+        a1, a2 = rng.uniform(0.02, 0.15, 2)
+        got = oracle_lib.disks_intersect(c1, n1, a1, c2, n2, a2)
+        if np.linalg.norm(c2 - c1) > a1 + a2:
+            assert not got
+            continue
+        ref, margin = _chords_overlap_ref(c1, n1, a1, c2, n2, a2)
+        if margin < 1e-9:
+            continue
+        assert got == ref
+        checked += 1
+        hits += ref
+    assert checked > 3000 and 0.1 * checked < hits < 0.9 * checked
+
+
+def test_disks_dense_sampling(oracle_lib):
+    """Tiny cases: sample disk 1 densely; a sample point lying (within a
+    tolerance) in plane 2 inside disk 2 proves intersection."""
+    rng = np.random.default_rng(5)
+    agree = 0
+    for _ in range(300):
+        c1 = np.array([0.5, 0.5, 0.5])
+        c2 = c1 + rng.uniform(-0.1, 0.1, 3)
+        n1, n2 = _rand_unit(rng), _rand_unit(rng)
+        a1, a2 = 0.08, 0.07
+        got = oracle_lib.disks_intersect(c1, n1, a1, c2, n2, a2)
+        e1 = np.cross(n1, [1.0, 0, 0] if abs(n1[0]) < 0.9 else [0, 1.0, 0])
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(n1, e1)
+        r = np.linspace(0, a1, 200)[:, None]
+        th = np.linspace(0, 2 * np.pi, 800)[None, :]
+        pts = c1[None, None, :] + (r * np.cos(th))[..., None] * e1 + (r * np.sin(th))[..., None] * e2
+        h = (pts - c2) @ n2
+        rad = np.linalg.norm((pts - c2) - h[..., None] * n2, axis=-1)
+        sampled = bool(np.any((np.abs(h) < 2e-4) & (rad <= a2)))
+        clear = bool(np.all((np.abs(h) > 2e-3) | (rad > a2 + 2e-3)))
+        if sampled:
+            assert got
+            agree += 1
+        elif clear:
+            assert not got
+            agree += 1
+    assert agree > 200
