@@ -1,0 +1,208 @@
+/*
+ * srm.h -- C ABI of the MI355X (gfx950) Swelling and Random Migration (SRM)
+ * library.
+ *
+ * SRM (Tarasovs, "Efficient generation of large-scale non-equilibrium
+ * distributions of particles", Sec. 2, Algorithms 1-6) grows the particles
+ * of a periodic box step by step and after each growth step moves every
+ * particle by a small random displacement, rejecting moves that overlap a
+ * neighbour, until the target volume fraction is reached without overlap.
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: SRM_OK (0) or a negative srm_status.  On error,
+ *    srm_last_error() returns a message (thread-local, valid until the next
+ *    call on the same thread).  No C++ exception crosses this boundary.
+ *  - Particle arrays are structure-of-arrays in particle-id order: a
+ *    position array holds dim * n doubles, x[0..n) then y[0..n) [then
+ *    z[0..n)]; normals hold 3 * n doubles the same way.
+ *  - mem_kind says where caller buffers live: SRM_MEM_HOST (pageable or
+ *    pinned host memory) or SRM_MEM_DEVICE (device memory of the context's
+ *    GPU, e.g. torch.Tensor.data_ptr()).  The caller owns every buffer it
+ *    passes; the library copies inputs and writes outputs, and never keeps a
+ *    caller pointer after the call returns.
+ *  - A context owns all of its device memory and runs every kernel on the
+ *    HIP stream given at srm_init (0 = the null stream).  Calls that return
+ *    host-visible results synchronise that stream before returning.  A
+ *    context is not thread-safe: calls on one context must not overlap.
+ *  - Random numbers: Philox4x64-10 with key (seed, 0) and counter
+ *    (particle id, sweep, kind<<48 | pass<<32 | trial<<16 | round, stream),
+ *    so a run is a pure function of (inputs, params, s0, sweep0): results do
+ *    not depend on launch shapes, and a saved state resumes bit-exactly.
+ */
+#ifndef SRM_H
+#define SRM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct srm_ctx srm_ctx;
+typedef int32_t srm_status;
+
+enum {
+    SRM_OK = 0,
+    SRM_EINVAL = -1,     /* bad argument; no side effects */
+    SRM_ENOMEM = -2,     /* device or host allocation failed */
+    SRM_EDEVICE = -3,    /* a HIP call failed */
+    SRM_EOVERLAP = -4,   /* initial configuration overlaps at s0 */
+    SRM_ENOTCONV = -5,   /* max_sweeps reached before s_target */
+    SRM_ECAPACITY = -6   /* output buffer too small; *count holds the need */
+};
+
+enum { SRM_BALL = 0, SRM_PLATELET = 1 };
+enum { SRM_MEM_HOST = 0, SRM_MEM_DEVICE = 1 };
+enum { SRM_PASS_MAIN = 0, SRM_PASS_SHAKE = 1 };
+
+/* Problem statement of Algorithm 1: box edges, particle set, target, the
+ * swelling and migration rates c_w and c_m and the attempt counts N_k, N_l
+ * (Sec. 2).  Radii are R_i = s * rho_i with a common scale s that grows from
+ * s0 to s_target. */
+typedef struct {
+    int32_t dim;         /* 2 (disks) or 3 (spheres, platelets) */
+    int32_t shape;       /* SRM_BALL, or SRM_PLATELET (3D only: thin disks) */
+    int64_t n;           /* particle count, 1 <= n < 2^31 */
+    double box[3];       /* periodic box edges L_a > 0 (box[2] unused in 2D) */
+    double s_target;     /* final radius scale (sets the target fraction) */
+    double c_w;          /* swelling step per sweep, as a fraction of s_target */
+    double c_m;          /* migration step length (absolute) */
+    double c_n;          /* platelet normal step (unit-vector length) */
+    double thick_ratio;  /* platelet thickness / diameter (volume only) */
+    int32_t n_k;         /* passes per sweep before a shake, 0..65535 */
+    int32_t n_l;         /* trial moves per particle per pass, 0..255 */
+    uint64_t seed;       /* Philox key */
+} srm_params;
+
+typedef struct {
+    int32_t committed;     /* 1: the swollen state was admitted; 0: shaken */
+    int32_t passes_main;   /* migration passes on the swollen copy */
+    int32_t passes_shake;  /* shake passes on the committed state */
+    int32_t grid[3];       /* cells per axis used by this sweep */
+    int64_t sweep;         /* sweep counter after the sweep */
+    double s;              /* radius scale after the sweep */
+    double fraction;       /* volume fraction at s */
+    int64_t n_failed_last; /* particles that rejected every trial in the last pass */
+} srm_sweep_info;
+
+typedef struct {
+    int64_t sweeps;        /* sweeps run by this call */
+    int64_t passes;        /* migration passes (main + shake) */
+    int64_t shakes;        /* sweeps that ended in a shake */
+    int64_t updates;       /* particle updates = n * passes */
+    double s, fraction;    /* final radius scale and volume fraction */
+} srm_run_info;
+
+/* Create a context.  p: parameters (copied).  pos: dim*n SoA positions in
+ * [0, L_a) per axis.  rho: n shape radii > 0, or NULL for all 1.
+ * normals: 3*n unit normals (platelets), else NULL.  s0: starting radius
+ * scale; sweep0: starting sweep counter (resume).  stream: hipStream_t or
+ * NULL.  Fails with SRM_EOVERLAP if two particles overlap at s0 (Algorithm 1
+ * starts from a non-overlapping set), SRM_EINVAL on a bad parameter or a
+ * coordinate outside the box.  *out is set only on success. */
+srm_status srm_init(const srm_params *p, const double *pos, const double *rho,
+                    const double *normals, double s0, int64_t sweep0, int32_t mem_kind,
+                    void *stream, srm_ctx **out);
+
+/* One iteration of Algorithm 1's main loop: swell to
+ * s' = min(s + c_w*s_target, s_target); up to n_k times bin (Algorithm 2),
+ * move every particle (Algorithm 3 over the 2^dim-colour cell schedule) and
+ * check for overlaps (Algorithm 6); on the first clean pass commit s'; else
+ * discard the swollen copy and shake the committed state (n_k passes at its
+ * own radii).  info may be NULL. */
+srm_status srm_sweep(srm_ctx *ctx, srm_sweep_info *info);
+
+/* Repeat srm_sweep until the committed scale equals s_target (Sec. 2 step
+ * e).  SRM_ENOTCONV after max_sweeps sweeps; the committed state is then the
+ * last admissible one.  info may be NULL. */
+srm_status srm_run_to_fraction(srm_ctx *ctx, int32_t max_sweeps, srm_run_info *info);
+
+/* Pairs i < j of the committed state (original ids) whose shapes come within
+ * `gap` of each other: balls with q_ij <= ((R_i + R_j) + gap)^2 under the
+ * minimum image; platelets (gap must be 0) whose disks intersect.  Written
+ * to ij as (i, j) int32 pairs sorted by (i, j); *count = number of pairs.
+ * SRM_ECAPACITY (nothing written) if *count > cap. */
+srm_status srm_pairs(srm_ctx *ctx, double gap, int64_t cap, int32_t *ij, int64_t *count,
+                     int32_t mem_kind);
+
+/* Histogram of centre distances over pairs i < j of the committed state:
+ * pair in bin b = (int)(r_ij * (nbins / r_max)) when b < nbins (r_ij is the
+ * correctly rounded sqrt of the minimum-image squared distance).  counts: n
+ * bins of uint64 (host).  g (host, nullable): counts normalised by the ideal
+ * gas count n(n-1)/2 * shell volume / box volume.  Requires 0 < r_max <=
+ * min(L_a)/2 and 1 <= nbins <= 65536. */
+srm_status srm_rdf(srm_ctx *ctx, int32_t nbins, double r_max, uint64_t *counts, double *g);
+
+/* Committed state in particle-id order: pos (dim*n), normals (3*n, or NULL),
+ * s, sweep (both nullable). */
+srm_status srm_get_state(srm_ctx *ctx, double *pos, double *normals, double *s,
+                         int64_t *sweep, int32_t mem_kind);
+
+/* Release the context and all of its device memory.  NULL is a no-op. */
+srm_status srm_free(srm_ctx *ctx);
+
+const char *srm_last_error(void);
+
+/* ---- step-level entry points (parity tests and diagnostics) ---------- */
+
+/* Cells per axis of the adaptive grid for radius scale s (Algorithm 1 cell
+ * size: 2.5 * R'max + 2.5 * c_m). */
+srm_status srm_grid(srm_ctx *ctx, double s, int32_t na[3]);
+
+/* Cell (linear index cx + Nx*(cy + Ny*cz)) of every committed particle in
+ * the grid for radius scale grid_s (Algorithm 2), in id order, host buffer. */
+srm_status srm_cells(srm_ctx *ctx, double grid_s, int32_t *cell_by_id);
+
+/* One bin + migration pass (Algorithms 2, 3) on the committed state in
+ * place, with the grid for grid_s, radii at scale radius_s, counter fields
+ * (kind, k) and the context's current sweep counter; then the global check
+ * (Algorithm 6).  acc_by_id (host, nullable): accepted trial per particle
+ * (0 = none).  overlap (nullable): 1 if any pair overlaps afterwards. */
+srm_status srm_pass(srm_ctx *ctx, double grid_s, double radius_s, int32_t kind, int32_t k,
+                    uint8_t *acc_by_id, int32_t *overlap);
+
+/* Accept codes of the last pass run by srm_sweep or srm_pass, id order. */
+srm_status srm_last_acc(srm_ctx *ctx, uint8_t *acc_by_id);
+
+/* ---- device-time profile ------------------------------------------------ */
+
+/* Device time of the sweep's kernels, measured with hipEvents recorded on
+ * the context's stream around each binning run (Algorithm 2), each colour
+ * phase of a migration pass (Algorithm 3) and each global check
+ * (Algorithm 6).  Milliseconds accumulate from the last srm_profile_enable. */
+typedef struct {
+    double ms_bin, ms_migrate, ms_check;
+    int64_t bins;              /* binning runs */
+    int64_t launches_migrate;  /* colour-phase launches */
+    int64_t passes;            /* migration passes */
+    int64_t checks;            /* global checks */
+} srm_profile;
+
+/* Switch profiling on (1) or off (0); resets the accumulated profile. */
+srm_status srm_profile_enable(srm_ctx *ctx, int32_t on);
+/* Copy the accumulated profile (synchronises the stream). */
+srm_status srm_profile_read(srm_ctx *ctx, srm_profile *out);
+
+/* ---- diagnostics of the device arithmetic ------------------------------ */
+
+/* Device results, for host arrays of n inputs, of IEEE binary64 sqrt(a[i])
+ * and a[i] / b[i] as the kernels compute them (the bit-exact contract needs
+ * both correctly rounded).  n >= 0; all buffers host memory. */
+srm_status srm_debug_fp(const double *a, const double *b, int64_t n, double *sqrt_out,
+                        double *div_out);
+
+/* Philox4x64-10 on the device: out[4i..4i+3] = philox(ctr[4i..4i+3],
+ * key[2i..2i+1]) for i < n.  Host buffers. */
+srm_status srm_debug_philox(const uint64_t *ctr, const uint64_t *key, int64_t n, uint64_t *out);
+
+/* The trial-move random vector (length len, dim 2 or 3) drawn on the device
+ * for particle ids 0..n-1 with sweep t and counter word
+ * kind<<48 | k<<32 | l<<16: out[3i..3i+2] (z = 0 in 2D).  Host buffer. */
+srm_status srm_debug_unitvec(int32_t dim, uint64_t seed, uint64_t t, uint64_t kkl,
+                             uint64_t stream, double len, int64_t n, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRM_H */

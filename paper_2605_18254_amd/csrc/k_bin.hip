@@ -1,0 +1,379 @@
+// k_bin.hip -- Algorithm 2 (build cell list) as a counting sort on gfx950:
+// cell ids + per-cell counts, an exclusive prefix scan of the counts
+// (wavefront shuffles, LDS for the wave totals), a scatter into cell-sorted
+// SoA arrays, and a per-cell fix-up that restores ascending particle ids
+// inside each cell (the atomic slot order is not deterministic; the order
+// within a cell is part of the sequential processing order).
+#include "srm_internal.hpp"
+
+namespace srm {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;  // elements per scan block
+
+__global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) a[i] = v;
+}
+
+__global__ void k_fill_u8(uint8_t *a, int64_t n, uint8_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) a[i] = v;
+}
+
+__global__ void k_zero_counters(Counters *c)
+{
+    if (threadIdx.x == 0) {
+        c->overlap = 0;
+        c->bad = 0;
+        c->nfail = 0;
+    }
+}
+
+__global__ void k_iota(int32_t *a, int32_t n)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = i;
+}
+
+// Cell id of each particle, its rank in the cell by atomic increment, and a
+// range check of the coordinates (a coordinate outside [0, L) or NaN sets
+// cnt->bad and is binned into cell 0 so that every index stays in bounds).
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_bin_count(const double *__restrict__ x,
+                                                      const double *__restrict__ y,
+                                                      const double *__restrict__ z, int32_t n,
+                                                      Grid g, int32_t *__restrict__ cell,
+                                                      int32_t *__restrict__ slot,
+                                                      int32_t *__restrict__ counts, Counters *cnt)
+{
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const double px = x[p], py = y[p], pz = (DIM == 3) ? z[p] : 0.0;
+    bool ok = (px >= 0.0 && px < g.box[0]) && (py >= 0.0 && py < g.box[1]);
+    if (DIM == 3) ok = ok && (pz >= 0.0 && pz < g.box[2]);
+    int32_t c = 0;
+    if (ok) {
+        c = cell_of<DIM>(g, px, py, pz);
+    } else {
+        cnt->bad = 1;
+    }
+    cell[p] = c;
+    slot[p] = atomicAdd(&counts[c], 1);
+}
+
+// Inclusive scan over the 64 lanes of a wavefront.
+__device__ __forceinline__ int32_t wave_inclusive_scan(int32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int32_t wave_sum(int32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Exclusive scan of one value per thread over a block of kBlock threads;
+// returns the prefix of the calling thread and sets *total.
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *lds_waves,
+                                                        int32_t *total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    constexpr int kWaves = kBlock / 64;
+    const int32_t inc = wave_inclusive_scan(v);
+    if (lane == 63) lds_waves[wid] = inc;
+    __syncthreads();
+    int32_t wave_off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const int32_t s = lds_waves[w];
+        if (w < wid) wave_off += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return wave_off + inc - v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_partials(const int32_t *__restrict__ in,
+                                                          int32_t m, int32_t *__restrict__ partials)
+{
+    __shared__ int32_t lds[kBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        if (i < m) s += in[i];
+    }
+    s = wave_sum(s);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) lds[wid] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += lds[w];
+        partials[blockIdx.x] = t;
+    }
+}
+
+// Single block: exclusive scan of the per-block sums in place, total into
+// out_total.
+__global__ void __launch_bounds__(kBlock) k_scan_top(int32_t *__restrict__ partials, int32_t nb,
+                                                     int32_t *__restrict__ out_total)
+{
+    __shared__ int32_t lds[kBlock / 64];
+    int32_t carry = 0;
+    for (int32_t base = 0; base < nb; base += kBlock) {
+        const int32_t i = base + threadIdx.x;
+        const int32_t v = (i < nb) ? partials[i] : 0;
+        int32_t tot;
+        const int32_t ex = block_exclusive_scan(v, lds, &tot);
+        if (i < nb) partials[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *out_total = carry;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_final(const int32_t *__restrict__ in, int32_t m,
+                                                       const int32_t *__restrict__ partials,
+                                                       int32_t *__restrict__ out)
+{
+    __shared__ int32_t lds[kBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t v[kScanItems];
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        v[k] = (i < m) ? in[i] : 0;
+        s += v[k];
+    }
+    int32_t tot;
+    int32_t run = partials[blockIdx.x] + block_exclusive_scan(s, lds, &tot);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        if (i < m) out[i] = run;
+        run += v[k];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_scatter(PBuf src, PBuf dst, int32_t n, int dim,
+                                                    const int32_t *__restrict__ cell,
+                                                    const int32_t *__restrict__ slot,
+                                                    const int32_t *__restrict__ start)
+{
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t d = start[cell[p]] + slot[p];
+    dst.x[0][d] = src.x[0][p];
+    dst.x[1][d] = src.x[1][p];
+    if (dim == 3) dst.x[2][d] = src.x[2][p];
+    dst.id[d] = src.id[p];
+    if (src.rho) dst.rho[d] = src.rho[p];
+    if (src.nrm[0]) {
+        dst.nrm[0][d] = src.nrm[0][p];
+        dst.nrm[1][d] = src.nrm[1][p];
+        dst.nrm[2][d] = src.nrm[2][p];
+    }
+}
+
+// Restore ascending ids within each cell (insertion sort of the cell's
+// slice; most slices are already ordered and are only read).
+__global__ void __launch_bounds__(kBlock) k_fixup(PBuf b, int dim, const int32_t *__restrict__ start,
+                                                  int32_t ncell)
+{
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int32_t beg = start[c], end = start[c + 1];
+    if (end - beg < 2) return;
+    bool sorted = true;
+    for (int32_t i = beg + 1; i < end; ++i) sorted = sorted && (b.id[i - 1] < b.id[i]);
+    if (sorted) return;
+    for (int32_t i = beg + 1; i < end; ++i) {
+        const int32_t key = b.id[i];
+        const double kx = b.x[0][i], ky = b.x[1][i], kz = (dim == 3) ? b.x[2][i] : 0.0;
+        const double kr = b.rho ? b.rho[i] : 0.0;
+        double kn0 = 0.0, kn1 = 0.0, kn2 = 0.0;
+        if (b.nrm[0]) { kn0 = b.nrm[0][i]; kn1 = b.nrm[1][i]; kn2 = b.nrm[2][i]; }
+        int32_t j = i - 1;
+        while (j >= beg && b.id[j] > key) {
+            b.id[j + 1] = b.id[j];
+            b.x[0][j + 1] = b.x[0][j];
+            b.x[1][j + 1] = b.x[1][j];
+            if (dim == 3) b.x[2][j + 1] = b.x[2][j];
+            if (b.rho) b.rho[j + 1] = b.rho[j];
+            if (b.nrm[0]) {
+                b.nrm[0][j + 1] = b.nrm[0][j];
+                b.nrm[1][j + 1] = b.nrm[1][j];
+                b.nrm[2][j + 1] = b.nrm[2][j];
+            }
+            --j;
+        }
+        b.id[j + 1] = key;
+        b.x[0][j + 1] = kx;
+        b.x[1][j + 1] = ky;
+        if (dim == 3) b.x[2][j + 1] = kz;
+        if (b.rho) b.rho[j + 1] = kr;
+        if (b.nrm[0]) { b.nrm[0][j + 1] = kn0; b.nrm[1][j + 1] = kn1; b.nrm[2][j + 1] = kn2; }
+    }
+}
+
+struct XPtrs {
+    const double *x[6];
+};
+
+__global__ void __launch_bounds__(kBlock) k_to_id_order(XPtrs xs, int nx, const int32_t *__restrict__ id,
+                                                        int32_t n, double *__restrict__ out)
+{
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int64_t i = id[p];
+    for (int a = 0; a < nx; ++a) out[(int64_t)a * n + i] = xs.x[a][p];
+}
+
+__global__ void __launch_bounds__(kBlock) k_u8_to_id_order(const uint8_t *__restrict__ a,
+                                                           const int32_t *__restrict__ id, int32_t n,
+                                                           uint8_t *__restrict__ out)
+{
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    out[id[p]] = a[p];
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_cells_by_id(PBuf b, int32_t n, Grid g, int32_t *__restrict__ out)
+{
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    out[b.id[p]] = cell_of<DIM>(g, b.x[0][p], b.x[1][p], DIM == 3 ? b.x[2][p] : 0.0);
+}
+
+inline unsigned blocks_for(int64_t n, int per = kBlock)
+{
+    int64_t b = (n + per - 1) / per;
+    return (unsigned)(b > 0 ? b : 1);
+}
+
+}  // namespace
+
+hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    unsigned nb = blocks_for(n);
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_fill_i32, dim3(nb), dim3(kBlock), 0, stream, a, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t *a, int64_t n, uint8_t v, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    unsigned nb = blocks_for(n);
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_fill_u8, dim3(nb), dim3(kBlock), 0, stream, a, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_counters(Counters *c, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, stream, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t *a, int32_t n, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota, dim3(blocks_for(n)), dim3(kBlock), 0, stream, a, n);
+    return hipGetLastError();
+}
+
+hipError_t scan_counts(const int32_t *counts, int32_t *start, int32_t *partials, int32_t m,
+                       hipStream_t stream)
+{
+    const unsigned nb = blocks_for(m, kScanTile);
+    hipLaunchKernelGGL(k_scan_partials, dim3(nb), dim3(kBlock), 0, stream, counts, m, partials);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, stream, partials, (int32_t)nb,
+                       start + m);
+    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kBlock), 0, stream, counts, m, partials,
+                       start);
+    return hipGetLastError();
+}
+
+hipError_t bin_particles(int dim, const PBuf &src, const PBuf &dst, int32_t n, const Grid &g,
+                         Scratch &sc, Counters *cnt, hipStream_t stream)
+{
+    if ((int64_t)g.ncell > sc.cap) return hipErrorInvalidValue;
+    hipError_t e = launch_fill_i32(sc.counts, g.ncell, 0, stream);
+    if (e != hipSuccess) return e;
+    if (n > 0) {
+        if (dim == 3)
+            hipLaunchKernelGGL(k_bin_count<3>, dim3(blocks_for(n)), dim3(kBlock), 0, stream,
+                               src.x[0], src.x[1], src.x[2], n, g, sc.cell, sc.slot, sc.counts,
+                               cnt);
+        else
+            hipLaunchKernelGGL(k_bin_count<2>, dim3(blocks_for(n)), dim3(kBlock), 0, stream,
+                               src.x[0], src.x[1], src.x[2], n, g, sc.cell, sc.slot, sc.counts,
+                               cnt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = scan_counts(sc.counts, sc.start, sc.partials, g.ncell, stream)) != hipSuccess) return e;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(kBlock), 0, stream, src, dst, n,
+                           dim, sc.cell, sc.slot, sc.start);
+        hipLaunchKernelGGL(k_fixup, dim3(blocks_for(g.ncell)), dim3(kBlock), 0, stream, dst, dim,
+                           sc.start, g.ncell);
+    }
+    return hipGetLastError();
+}
+
+hipError_t to_id_order(const double *const *x, int nx, const int32_t *id, int32_t n, double *out,
+                       hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    XPtrs xs{};
+    for (int a = 0; a < nx && a < 6; ++a) xs.x[a] = x[a];
+    hipLaunchKernelGGL(k_to_id_order, dim3(blocks_for(n)), dim3(kBlock), 0, stream, xs, nx, id, n,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t u8_to_id_order(const uint8_t *a, const int32_t *id, int32_t n, uint8_t *out,
+                          hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_u8_to_id_order, dim3(blocks_for(n)), dim3(kBlock), 0, stream, a, id, n,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t cells_by_id(int dim, const PBuf &b, int32_t n, const Grid &g, int32_t *out,
+                       hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    if (dim == 3)
+        hipLaunchKernelGGL(k_cells_by_id<3>, dim3(blocks_for(n)), dim3(kBlock), 0, stream, b, n, g,
+                           out);
+    else
+        hipLaunchKernelGGL(k_cells_by_id<2>, dim3(blocks_for(n)), dim3(kBlock), 0, stream, b, n, g,
+                           out);
+    return hipGetLastError();
+}
+
+}  // namespace srm

@@ -1,0 +1,378 @@
+// k_migrate.hip -- Algorithm 3 (move particles) with Algorithm 5 (collision
+// check) over the 2^dim-colour cell schedule, and the global check of
+// Algorithm 6.
+//
+// Schedule: one launch per colour g; a thread owns one cell whose parity
+// vector is g and processes that cell's particles in ascending id order,
+// each with up to N_l trial moves.  Cells of one colour are at least two
+// cells apart on some axis, so no thread reads a cell another thread of the
+// same launch writes, and the launch equals any sequential order of its
+// cells.  The stencil is taken around the particle's binned cell; with a cell
+// edge >= 2.5 R'max + 2.5 c_m every particle within R_i + R_j of a trial
+// position is inside it, so each accept/reject decision equals the
+// all-pairs test.
+//
+// Interior cells (2 <= c_a <= N_a - 3 on every axis, all N_a >= 8) cannot
+// see a periodic image: neither the trial position nor any candidate has
+// wrapped, and all differences are below L/2, so the minimum-image
+// correction is the identity there and is skipped.
+#include "srm_internal.hpp"
+
+namespace srm {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <int DIM>
+struct Rows {
+    static constexpr int kRows = (DIM == 3) ? 9 : 3;
+    static constexpr int kRanges = 2 * kRows;  // a row of 3 cells is <= 2 slices
+};
+
+__device__ __forceinline__ int32_t wrap_index(int32_t c, int32_t n)
+{
+    c += (c < 0) ? n : 0;
+    c -= (c >= n) ? n : 0;
+    return c;
+}
+
+// Slices of the cell-sorted arrays covering the 3^dim cells around
+// (cx, cy, cz).  Cells (cx-1, cx, cx+1) of one row are consecutive in the
+// linear order unless the row wraps, so a row is one slice, or two at the
+// x boundary.  Axes with a single cell contribute only offset 0.
+template <int DIM>
+__device__ __forceinline__ void stencil_slices(const Grid &g, const int32_t *__restrict__ start,
+                                               int32_t cx, int32_t cy, int32_t cz, int32_t *lo,
+                                               int32_t *hi)
+{
+    const int32_t na0 = g.na[0], na1 = g.na[1], na2 = g.na[2];
+#pragma unroll
+    for (int iz = 0; iz < (DIM == 3 ? 3 : 1); ++iz) {
+#pragma unroll
+        for (int iy = 0; iy < 3; ++iy) {
+            const int r = (iz * 3 + iy) * 2;
+            lo[r] = hi[r] = lo[r + 1] = hi[r + 1] = 0;
+            const int32_t dy = iy - 1, dz = (DIM == 3) ? iz - 1 : 0;
+            if (na1 < 4 && dy != 0) continue;
+            if (DIM == 3 && na2 < 4 && dz != 0) continue;
+            const int32_t yy = wrap_index(cy + dy, na1);
+            const int32_t zz = (DIM == 3) ? wrap_index(cz + dz, na2) : 0;
+            const int32_t row = na0 * (yy + na1 * zz);
+            if (na0 < 4) {
+                lo[r] = start[row];
+                hi[r] = start[row + 1];
+            } else if (cx >= 1 && cx <= na0 - 2) {
+                lo[r] = start[row + cx - 1];
+                hi[r] = start[row + cx + 2];
+            } else if (cx == 0) {
+                lo[r] = start[row];
+                hi[r] = start[row + 2];
+                lo[r + 1] = start[row + na0 - 1];
+                hi[r + 1] = start[row + na0];
+            } else {
+                lo[r] = start[row + na0 - 2];
+                hi[r] = start[row + na0];
+                lo[r + 1] = start[row];
+                hi[r + 1] = start[row + 1];
+            }
+        }
+    }
+}
+
+// Does a ball of radius Ri at (yx, yy, yz) overlap any particle of the
+// slices other than slot `self`?  q = (dx*dx + dy*dy) + dz*dz <= (Ri+Rj)^2.
+template <int DIM, bool POLY, bool GENERAL>
+__device__ __forceinline__ bool ball_hits(const PassArgs &a, const int32_t *lo, const int32_t *hi,
+                                          int32_t self, double yx, double yy, double yz, double Ri)
+{
+    const double *__restrict__ X = a.buf.x[0];
+    const double *__restrict__ Y = a.buf.x[1];
+    const double *__restrict__ Z = a.buf.x[2];
+#pragma unroll
+    for (int r = 0; r < Rows<DIM>::kRanges; ++r) {
+        for (int32_t q = lo[r]; q < hi[r]; ++q) {
+            if (q == self) continue;
+            double dx = yx - X[q];
+            double dy = yy - Y[q];
+            if (GENERAL) {
+                dx = min_image(dx, a.g.box[0], a.g.half[0]);
+                dy = min_image(dy, a.g.box[1], a.g.half[1]);
+            }
+            double qq = dx * dx + dy * dy;
+            if (DIM == 3) {
+                double dz = yz - Z[q];
+                if (GENERAL) dz = min_image(dz, a.g.box[2], a.g.half[2]);
+                qq = qq + dz * dz;
+            }
+            double sig2;
+            if (POLY) {
+                const double sig = Ri + a.s * a.buf.rho[q];
+                sig2 = sig * sig;
+            } else {
+                sig2 = a.sig2_mono;
+            }
+            if (qq <= sig2) return true;
+        }
+    }
+    return false;
+}
+
+template <int DIM>
+__device__ __forceinline__ bool is_interior(const Grid &g, int32_t cx, int32_t cy, int32_t cz)
+{
+    bool in = g.na[0] >= 8 && g.na[1] >= 8 && cx >= 2 && cx <= g.na[0] - 3 && cy >= 2 &&
+              cy <= g.na[1] - 3;
+    if (DIM == 3) in = in && g.na[2] >= 8 && cz >= 2 && cz <= g.na[2] - 3;
+    return in;
+}
+
+template <int DIM, bool POLY>
+__global__ void __launch_bounds__(kBlock) k_migrate_ball(PassArgs a, ColourLattice L)
+{
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= L.count) return;
+    const int32_t jx = t % L.h[0];
+    const int32_t r1 = t / L.h[0];
+    const int32_t jy = r1 % L.h[1];
+    const int32_t jz = r1 / L.h[1];
+    const int32_t cx = 2 * jx + L.off[0];
+    const int32_t cy = 2 * jy + L.off[1];
+    const int32_t cz = (DIM == 3) ? 2 * jz + L.off[2] : 0;
+    const int32_t c = cx + a.g.na[0] * (cy + a.g.na[1] * cz);
+    const int32_t beg = a.start[c], end = a.start[c + 1];
+    if (beg == end) return;
+    int32_t lo[Rows<DIM>::kRanges], hi[Rows<DIM>::kRanges];
+    stencil_slices<DIM>(a.g, a.start, cx, cy, cz, lo, hi);
+    const bool general = !is_interior<DIM>(a.g, cx, cy, cz);
+    double *__restrict__ X = a.buf.x[0];
+    double *__restrict__ Y = a.buf.x[1];
+    double *__restrict__ Z = a.buf.x[2];
+    for (int32_t p = beg; p < end; ++p) {
+        const double ox = X[p], oy = Y[p], oz = (DIM == 3) ? Z[p] : 0.0;
+        const uint64_t id = (uint64_t)a.buf.id[p];
+        const double Ri = POLY ? a.s * a.buf.rho[p] : a.s;
+        uint8_t code = 0;
+        for (int32_t l = 1; l <= a.n_l; ++l) {
+            double v[3];
+            unit_vector<DIM>(a.seed, id, a.t, a.kk | ((uint64_t)l << 16), 0, a.c_m, v);
+            const double yx = wrap_coord(ox + v[0], a.g.box[0]);
+            const double yy = wrap_coord(oy + v[1], a.g.box[1]);
+            const double yz = (DIM == 3) ? wrap_coord(oz + v[2], a.g.box[2]) : 0.0;
+            const bool hit = general ? ball_hits<DIM, POLY, true>(a, lo, hi, p, yx, yy, yz, Ri)
+                                     : ball_hits<DIM, POLY, false>(a, lo, hi, p, yx, yy, yz, Ri);
+            if (!hit) {
+                X[p] = yx;
+                Y[p] = yy;
+                if (DIM == 3) Z[p] = yz;
+                code = (uint8_t)l;
+                break;
+            }
+        }
+        a.acc[p] = code;
+    }
+}
+
+// Algorithm 6 after a pass: some pair overlaps iff some particle that
+// rejected all of its trials overlaps another one (a particle that accepted
+// a trial was tested against every particle processed before it at its final
+// position and every later one at a position it kept if it was rejected).
+// So only particles with accept code 0 are tested; check_all tests every
+// particle (initial-state validation).
+template <int DIM, bool POLY>
+__global__ void __launch_bounds__(kBlock) k_check_ball(PassArgs a, int32_t check_all, Counters *cnt)
+{
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool failed = (p < a.n) && (check_all || a.acc[p] == 0);
+    const unsigned long long m = __ballot(failed);
+    if ((threadIdx.x & 63) == 0 && m != 0ull)
+        atomicAdd((unsigned long long *)&cnt->nfail, (unsigned long long)__popcll(m));
+    if (!failed) return;
+    const double x = a.buf.x[0][p], y = a.buf.x[1][p];
+    const double z = (DIM == 3) ? a.buf.x[2][p] : 0.0;
+    const int32_t cx = cell_coord(x, a.g.inv_w[0], a.g.na[0]);
+    const int32_t cy = cell_coord(y, a.g.inv_w[1], a.g.na[1]);
+    const int32_t cz = (DIM == 3) ? cell_coord(z, a.g.inv_w[2], a.g.na[2]) : 0;
+    int32_t lo[Rows<DIM>::kRanges], hi[Rows<DIM>::kRanges];
+    stencil_slices<DIM>(a.g, a.start, cx, cy, cz, lo, hi);
+    const double Ri = POLY ? a.s * a.buf.rho[p] : a.s;
+    if (ball_hits<DIM, POLY, true>(a, lo, hi, p, x, y, z, Ri)) atomicOr(&cnt->overlap, 1);
+}
+
+// ---------------------------------------------------------------- platelets
+
+// Thin platelets (3D): the trial moves the centre by c_m times a random
+// unit vector (stream 0) and the normal to (n + c_n w) / |n + c_n w| (w a
+// random unit vector, stream 1); both are accepted or rejected together.
+// The pair test is the exact disk-disk intersection with the lower id as
+// disk 1.
+__device__ __forceinline__ bool platelet_hits(const PassArgs &a, const int32_t *lo,
+                                              const int32_t *hi, int32_t self, int32_t self_id,
+                                              double yx, double yy, double yz, const double ny[3],
+                                              double ai)
+{
+    const double *__restrict__ X = a.buf.x[0];
+    const double *__restrict__ Y = a.buf.x[1];
+    const double *__restrict__ Z = a.buf.x[2];
+#pragma unroll
+    for (int r = 0; r < Rows<3>::kRanges; ++r) {
+        for (int32_t q = lo[r]; q < hi[r]; ++q) {
+            if (q == self) continue;
+            const double aj = a.buf.rho ? a.s * a.buf.rho[q] : a.s;
+            const double nq[3] = {a.buf.nrm[0][q], a.buf.nrm[1][q], a.buf.nrm[2][q]};
+            const int32_t qid = a.buf.id[q];
+            bool hit;
+            if (self_id < qid) {
+                const double dx = min_image(X[q] - yx, a.g.box[0], a.g.half[0]);
+                const double dy = min_image(Y[q] - yy, a.g.box[1], a.g.half[1]);
+                const double dz = min_image(Z[q] - yz, a.g.box[2], a.g.half[2]);
+                hit = disks_intersect(dx, dy, dz, ny, ai, nq, aj);
+            } else {
+                const double dx = min_image(yx - X[q], a.g.box[0], a.g.half[0]);
+                const double dy = min_image(yy - Y[q], a.g.box[1], a.g.half[1]);
+                const double dz = min_image(yz - Z[q], a.g.box[2], a.g.half[2]);
+                hit = disks_intersect(dx, dy, dz, nq, aj, ny, ai);
+            }
+            if (hit) return true;
+        }
+    }
+    return false;
+}
+
+__global__ void __launch_bounds__(kBlock) k_migrate_platelet(PassArgs a, ColourLattice L)
+{
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= L.count) return;
+    const int32_t jx = t % L.h[0];
+    const int32_t r1 = t / L.h[0];
+    const int32_t jy = r1 % L.h[1];
+    const int32_t jz = r1 / L.h[1];
+    const int32_t cx = 2 * jx + L.off[0];
+    const int32_t cy = 2 * jy + L.off[1];
+    const int32_t cz = 2 * jz + L.off[2];
+    const int32_t c = cx + a.g.na[0] * (cy + a.g.na[1] * cz);
+    const int32_t beg = a.start[c], end = a.start[c + 1];
+    if (beg == end) return;
+    int32_t lo[Rows<3>::kRanges], hi[Rows<3>::kRanges];
+    stencil_slices<3>(a.g, a.start, cx, cy, cz, lo, hi);
+    double *__restrict__ X = a.buf.x[0];
+    double *__restrict__ Y = a.buf.x[1];
+    double *__restrict__ Z = a.buf.x[2];
+    for (int32_t p = beg; p < end; ++p) {
+        const double ox = X[p], oy = Y[p], oz = Z[p];
+        const double n0 = a.buf.nrm[0][p], n1 = a.buf.nrm[1][p], n2 = a.buf.nrm[2][p];
+        const int32_t pid = a.buf.id[p];
+        const double ai = a.buf.rho ? a.s * a.buf.rho[p] : a.s;
+        uint8_t code = 0;
+        for (int32_t l = 1; l <= a.n_l; ++l) {
+            const uint64_t kkl = a.kk | ((uint64_t)l << 16);
+            double v[3], w[3];
+            unit_vector<3>(a.seed, (uint64_t)pid, a.t, kkl, 0, a.c_m, v);
+            const double yx = wrap_coord(ox + v[0], a.g.box[0]);
+            const double yy = wrap_coord(oy + v[1], a.g.box[1]);
+            const double yz = wrap_coord(oz + v[2], a.g.box[2]);
+            unit_vector<3>(a.seed, (uint64_t)pid, a.t, kkl, 1, a.c_n, w);
+            const double m0 = n0 + w[0], m1 = n1 + w[1], m2 = n2 + w[2];
+            const double mm = m0 * m0 + m1 * m1 + m2 * m2;
+            const double inv = 1.0 / __builtin_sqrt(mm);
+            const double ny[3] = {m0 * inv, m1 * inv, m2 * inv};
+            if (!platelet_hits(a, lo, hi, p, pid, yx, yy, yz, ny, ai)) {
+                X[p] = yx;
+                Y[p] = yy;
+                Z[p] = yz;
+                a.buf.nrm[0][p] = ny[0];
+                a.buf.nrm[1][p] = ny[1];
+                a.buf.nrm[2][p] = ny[2];
+                code = (uint8_t)l;
+                break;
+            }
+        }
+        a.acc[p] = code;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_check_platelet(PassArgs a, int32_t check_all,
+                                                           Counters *cnt)
+{
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool failed = (p < a.n) && (check_all || a.acc[p] == 0);
+    const unsigned long long m = __ballot(failed);
+    if ((threadIdx.x & 63) == 0 && m != 0ull)
+        atomicAdd((unsigned long long *)&cnt->nfail, (unsigned long long)__popcll(m));
+    if (!failed) return;
+    const double x = a.buf.x[0][p], y = a.buf.x[1][p], z = a.buf.x[2][p];
+    const double np_[3] = {a.buf.nrm[0][p], a.buf.nrm[1][p], a.buf.nrm[2][p]};
+    const int32_t cx = cell_coord(x, a.g.inv_w[0], a.g.na[0]);
+    const int32_t cy = cell_coord(y, a.g.inv_w[1], a.g.na[1]);
+    const int32_t cz = cell_coord(z, a.g.inv_w[2], a.g.na[2]);
+    int32_t lo[Rows<3>::kRanges], hi[Rows<3>::kRanges];
+    stencil_slices<3>(a.g, a.start, cx, cy, cz, lo, hi);
+    const double ai = a.buf.rho ? a.s * a.buf.rho[p] : a.s;
+    if (platelet_hits(a, lo, hi, p, a.buf.id[p], x, y, z, np_, ai)) atomicOr(&cnt->overlap, 1);
+}
+
+inline unsigned blocks_for(int64_t n)
+{
+    int64_t b = (n + kBlock - 1) / kBlock;
+    return (unsigned)(b > 0 ? b : 1);
+}
+
+bool colour_lattice(int dim, const Grid &g, int colour, ColourLattice &L)
+{
+    L.count = 1;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int bit = (colour >> ax) & 1;
+        if (ax < dim && g.na[ax] >= 4) {
+            L.h[ax] = g.na[ax] / 2;
+            L.off[ax] = bit;
+        } else {
+            if (bit) return false;
+            L.h[ax] = 1;
+            L.off[ax] = 0;
+        }
+        L.count *= L.h[ax];
+    }
+    return L.count > 0;
+}
+
+}  // namespace
+
+hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int colour,
+                          hipStream_t stream, bool *launched)
+{
+    ColourLattice L;
+    *launched = false;
+    if (!colour_lattice(dim, a.g, colour, L)) return hipSuccess;
+    const dim3 grid(blocks_for(L.count)), block(kBlock);
+    if (shape == SRM_PLATELET) {
+        hipLaunchKernelGGL(k_migrate_platelet, grid, block, 0, stream, a, L);
+    } else if (dim == 3) {
+        if (poly) hipLaunchKernelGGL((k_migrate_ball<3, true>), grid, block, 0, stream, a, L);
+        else hipLaunchKernelGGL((k_migrate_ball<3, false>), grid, block, 0, stream, a, L);
+    } else {
+        if (poly) hipLaunchKernelGGL((k_migrate_ball<2, true>), grid, block, 0, stream, a, L);
+        else hipLaunchKernelGGL((k_migrate_ball<2, false>), grid, block, 0, stream, a, L);
+    }
+    *launched = true;
+    return hipGetLastError();
+}
+
+hipError_t check_overlaps(int dim, int shape, bool poly, const PassArgs &a, bool check_all,
+                          Counters *cnt, hipStream_t stream)
+{
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid(blocks_for(a.n)), block(kBlock);
+    const int32_t all = check_all ? 1 : 0;
+    if (shape == SRM_PLATELET) {
+        hipLaunchKernelGGL(k_check_platelet, grid, block, 0, stream, a, all, cnt);
+    } else if (dim == 3) {
+        if (poly) hipLaunchKernelGGL((k_check_ball<3, true>), grid, block, 0, stream, a, all, cnt);
+        else hipLaunchKernelGGL((k_check_ball<3, false>), grid, block, 0, stream, a, all, cnt);
+    } else {
+        if (poly) hipLaunchKernelGGL((k_check_ball<2, true>), grid, block, 0, stream, a, all, cnt);
+        else hipLaunchKernelGGL((k_check_ball<2, false>), grid, block, 0, stream, a, all, cnt);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace srm

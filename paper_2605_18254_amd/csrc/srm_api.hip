@@ -1,0 +1,677 @@
+// srm_api.hip -- the C ABI of libsrm: context lifetime, Algorithm 1's sweep
+// driver on the host, state I/O.  Every step of the sweep runs in the HIP
+// kernels of k_bin.hip and k_migrate.hip on the context's stream; the host
+// only computes the per-sweep scalars (swelling, adaptive grid) and reads
+// back one small counter block per pass.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "srm_internal.hpp"
+
+using namespace srm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+srm_status fail(srm_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+srm_status fail(srm_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(SRM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+}  // namespace
+
+struct srm_ctx {
+    srm_params p{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int32_t n = 0;
+    int dim = 2;
+    bool poly = false, plate = false;
+    double rho_max = 1.0;
+    double sum_rho_d = 0.0;  // sum of rho_i^dim (fraction)
+    double s = 0.0;
+    int64_t t = 0;
+    PBuf P{}, Q{}, T{};
+    Scratch sc{};
+    uint8_t *acc = nullptr;
+    bool acc_valid = false;
+    PBuf acc_buf{};          // storage order the acc codes refer to
+    Counters *dcnt = nullptr;
+    Counters *hcnt = nullptr;  // pinned
+    double *dtmp = nullptr;    // 3n doubles: id-order staging
+    int32_t *itmp = nullptr;   // n ints
+    int64_t ncap = 0;
+    void *allocs[64];
+    int nalloc = 0;
+
+    // Optional device-time profile (hipEvents on the context's stream).
+    bool prof_on = false;
+    srm_profile prof{};
+    std::vector<hipEvent_t> ev_free;
+    struct Pending {
+        int kind;  // 0 bin, 1 migrate, 2 check
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+
+    template <class T_>
+    hipError_t alloc(T_ **ptr, size_t count)
+    {
+        void *v = nullptr;
+        hipError_t e = hipMalloc(&v, (count > 0 ? count : 1) * sizeof(T_));
+        if (e == hipSuccess) {
+            allocs[nalloc++] = v;
+            *ptr = (T_ *)v;
+        }
+        return e;
+    }
+    ~srm_ctx()
+    {
+        for (int i = 0; i < nalloc; ++i) (void)hipFree(allocs[i]);
+        if (hcnt) (void)hipHostFree(hcnt);
+        for (auto &p_ : pending) {
+            (void)hipEventDestroy(p_.a);
+            (void)hipEventDestroy(p_.b);
+        }
+        for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
+    }
+    hipEvent_t event()
+    {
+        if (!ev_free.empty()) {
+            hipEvent_t e = ev_free.back();
+            ev_free.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    // Record an event on the stream (profiling only); null when off.
+    hipEvent_t mark()
+    {
+        if (!prof_on) return nullptr;
+        hipEvent_t e = event();
+        if (e && hipEventRecord(e, stream) != hipSuccess) {
+            ev_free.push_back(e);
+            return nullptr;
+        }
+        return e;
+    }
+    void span(int kind, hipEvent_t a, hipEvent_t b)
+    {
+        if (a && b) pending.push_back({kind, a, b});
+    }
+    // After a stream synchronisation: fold completed spans into prof.
+    void resolve()
+    {
+        for (auto &p_ : pending) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p_.a, p_.b) == hipSuccess) {
+                if (p_.kind == 0) prof.ms_bin += ms;
+                else if (p_.kind == 1) prof.ms_migrate += ms;
+                else prof.ms_check += ms;
+            }
+            release(p_.a);
+            release(p_.b);
+        }
+        pending.clear();
+    }
+    void release(hipEvent_t e)
+    {
+        if (e) ev_free.push_back(e);
+    }
+};
+
+namespace {
+
+// Largest even m with m^dim <= n (caps the cell count near n for tiny radii).
+int64_t cell_cap(int dim, int64_t n)
+{
+    int64_t m = 0;
+    for (;;) {
+        const int64_t c = m + 2;
+        int64_t pw = 1;
+        for (int a = 0; a < dim; ++a) pw *= c;
+        if (pw > n) break;
+        m = c;
+    }
+    return m;
+}
+
+// Adaptive grid of Algorithm 1 for the largest radius rmax: cell edge
+// cs = 2.5 rmax + 2.5 c_m; per axis N_a = m - (m mod 2) cells if
+// m = min(floor(L_a / cs), ncap) >= 4, else one cell.
+Grid make_grid(const srm_ctx *c, double rmax)
+{
+    Grid g{};
+    const double cs = 2.5 * rmax + 2.5 * c->p.c_m;
+    for (int a = 0; a < 3; ++a) {
+        g.box[a] = c->p.box[a];
+        g.half[a] = 0.5 * c->p.box[a];
+        if (a >= c->dim) {
+            g.na[a] = 1;
+            g.inv_w[a] = 1.0 / c->p.box[a];
+            continue;
+        }
+        int64_t m;
+        const double q = (cs > 0.0) ? c->p.box[a] / cs : 0.0;
+        if (!(cs > 0.0) || q >= (double)c->ncap) m = c->ncap;
+        else m = (int64_t)q;
+        g.na[a] = (int32_t)((m >= 4) ? m - (m & 1) : 1);
+        g.inv_w[a] = (double)g.na[a] / c->p.box[a];
+    }
+    g.ncell = g.na[0] * g.na[1] * g.na[2];
+    return g;
+}
+
+double fraction_at(const srm_ctx *c, double s)
+{
+    double vbox = 1.0;
+    for (int a = 0; a < c->dim; ++a) vbox *= c->p.box[a];
+    double sd = 1.0;
+    for (int a = 0; a < c->dim; ++a) sd *= s;
+    double coeff;
+    if (c->plate) coeff = 2.0 * M_PI * c->p.thick_ratio;  // pi a^2 (thick_ratio 2a)
+    else coeff = (c->dim == 2) ? M_PI : 4.0 * M_PI / 3.0;
+    return coeff * sd * c->sum_rho_d / vbox;
+}
+
+double swell(const srm_ctx *c, double s)
+{
+    const double ds = c->p.c_w * c->p.s_target;
+    const double s1 = s + ds;
+    return (s1 < c->p.s_target) ? s1 : c->p.s_target;
+}
+
+hipError_t alloc_buf(srm_ctx *c, PBuf &b)
+{
+    hipError_t e;
+    for (int a = 0; a < c->dim; ++a)
+        if ((e = c->alloc(&b.x[a], c->n)) != hipSuccess) return e;
+    if ((e = c->alloc(&b.id, c->n)) != hipSuccess) return e;
+    if (c->poly && (e = c->alloc(&b.rho, c->n)) != hipSuccess) return e;
+    if (c->plate)
+        for (int a = 0; a < 3; ++a)
+            if ((e = c->alloc(&b.nrm[a], c->n)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+srm_status bin(srm_ctx *c, const PBuf &src, const PBuf &dst, const Grid &g)
+{
+    hipEvent_t e0 = c->mark();
+    HIP_TRY(bin_particles(c->dim, src, dst, c->n, g, c->sc, c->dcnt, c->stream));
+    c->span(0, e0, c->mark());
+    if (c->prof_on) c->prof.bins += 1;
+    return SRM_OK;
+}
+
+PassArgs pass_args(srm_ctx *c, const PBuf &b, const Grid &g, double s, int kind, int k)
+{
+    PassArgs a{};
+    a.buf = b;
+    a.start = c->sc.start;
+    a.acc = c->acc;
+    a.g = g;
+    a.n = c->n;
+    a.s = s;
+    const double sig = s + s;
+    a.sig2_mono = sig * sig;
+    a.seed = c->p.seed;
+    a.t = (uint64_t)c->t;
+    a.kk = ((uint64_t)(uint32_t)kind << 48) | ((uint64_t)(uint32_t)k << 32);
+    a.n_l = c->p.n_l;
+    a.c_m = c->p.c_m;
+    a.c_n = c->p.c_n;
+    return a;
+}
+
+// One migration pass on b (already binned with g), then the reduced global
+// check; returns the overlap flag and failure count through *ov / *nfail.
+srm_status run_pass(srm_ctx *c, const PBuf &b, const Grid &g, double s, int kind, int k,
+                    bool want_check, int32_t *ov, int64_t *nfail)
+{
+    const PassArgs a = pass_args(c, b, g, s, kind, k);
+    hipEvent_t e0 = c->mark();
+    for (int colour = 0; colour < (1 << c->dim); ++colour) {
+        bool launched = false;
+        HIP_TRY(migrate_colour(c->dim, c->p.shape, c->poly, a, colour, c->stream, &launched));
+        if (launched) {
+            hipEvent_t e1 = c->mark();
+            c->span(1, e0, e1);
+            e0 = e1 ? c->mark() : nullptr;
+            if (c->prof_on) c->prof.launches_migrate += 1;
+        }
+    }
+    if (e0) c->release(e0);
+    if (c->prof_on) c->prof.passes += 1;
+    c->acc_valid = true;
+    c->acc_buf = b;
+    if (!want_check) return SRM_OK;
+    HIP_TRY(launch_zero_counters(c->dcnt, c->stream));
+    hipEvent_t e2 = c->mark();
+    HIP_TRY(check_overlaps(c->dim, c->p.shape, c->poly, a, false, c->dcnt, c->stream));
+    c->span(2, e2, c->mark());
+    if (c->prof_on) c->prof.checks += 1;
+    HIP_TRY(hipMemcpyAsync(c->hcnt, c->dcnt, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->resolve();
+    if (ov) *ov = c->hcnt->overlap;
+    if (nfail) *nfail = c->hcnt->nfail;
+    return SRM_OK;
+}
+
+srm_status check_params(const srm_params *p)
+{
+    if (!p) return fail(SRM_EINVAL, "params is NULL");
+    if (p->dim != 2 && p->dim != 3) return fail(SRM_EINVAL, "dim must be 2 or 3");
+    if (p->shape != SRM_BALL && p->shape != SRM_PLATELET) return fail(SRM_EINVAL, "bad shape");
+    if (p->shape == SRM_PLATELET && p->dim != 3) return fail(SRM_EINVAL, "platelets are 3D");
+    if (p->n < 1 || p->n > 0x7fffffffLL) return fail(SRM_EINVAL, "n out of range");
+    for (int a = 0; a < p->dim; ++a)
+        if (!(p->box[a] > 0.0) || !isfinite(p->box[a])) return fail(SRM_EINVAL, "box edge <= 0");
+    if (!(p->s_target >= 0.0) || !isfinite(p->s_target)) return fail(SRM_EINVAL, "bad s_target");
+    if (!(p->c_w >= 0.0) || !(p->c_m >= 0.0) || !(p->c_n >= 0.0) || !isfinite(p->c_m) ||
+        !isfinite(p->c_w) || !isfinite(p->c_n))
+        return fail(SRM_EINVAL, "rates must be finite and >= 0");
+    if (p->n_k < 0 || p->n_k > 65535) return fail(SRM_EINVAL, "n_k out of range");
+    if (p->n_l < 0 || p->n_l > 255) return fail(SRM_EINVAL, "n_l out of range");
+    return SRM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *srm_last_error(void) { return g_last_error.c_str(); }
+
+srm_status srm_init(const srm_params *p, const double *pos, const double *rho,
+                    const double *normals, double s0, int64_t sweep0, int32_t mem_kind,
+                    void *stream, srm_ctx **out)
+{
+    srm_status st = check_params(p);
+    if (st) return st;
+    if (!pos || !out) return fail(SRM_EINVAL, "pos and out must not be NULL");
+    if (mem_kind != SRM_MEM_HOST && mem_kind != SRM_MEM_DEVICE)
+        return fail(SRM_EINVAL, "bad mem_kind");
+    if (p->shape == SRM_PLATELET && !normals) return fail(SRM_EINVAL, "platelets need normals");
+    if (!(s0 >= 0.0) || !isfinite(s0)) return fail(SRM_EINVAL, "bad s0");
+    if (sweep0 < 0) return fail(SRM_EINVAL, "sweep0 < 0");
+
+    srm_ctx *c = new (std::nothrow) srm_ctx();
+    if (!c) return fail(SRM_ENOMEM, "host allocation failed");
+    c->p = *p;
+    if (c->p.dim == 2) c->p.box[2] = 1.0;
+    c->n = (int32_t)p->n;
+    c->dim = p->dim;
+    c->plate = p->shape == SRM_PLATELET;
+    c->poly = rho != nullptr;
+    c->s = s0;
+    c->t = sweep0;
+    c->stream = (hipStream_t)stream;
+    c->ncap = cell_cap(c->dim, c->n);
+    auto bail = [&](srm_status s_) { delete c; return s_; };
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(SRM_EDEVICE, "no HIP device"));
+
+    const size_t n = (size_t)c->n;
+    hipError_t e = hipSuccess;
+    if ((e = alloc_buf(c, c->P)) || (e = alloc_buf(c, c->Q)) || (e = alloc_buf(c, c->T)) ||
+        (e = c->alloc(&c->sc.cell, n)) || (e = c->alloc(&c->sc.slot, n)) ||
+        (e = c->alloc(&c->acc, n)) || (e = c->alloc(&c->dtmp, 3 * n)) ||
+        (e = c->alloc(&c->itmp, n)) || (e = c->alloc(&c->dcnt, 1)))
+        return bail(fail(SRM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
+    c->sc.cap = (int64_t)n + 2;
+    if ((e = c->alloc(&c->sc.counts, (size_t)c->sc.cap)) ||
+        (e = c->alloc(&c->sc.start, (size_t)c->sc.cap + 1)) ||
+        (e = c->alloc(&c->sc.partials, (size_t)(c->sc.cap / 2048 + 2))))
+        return bail(fail(SRM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
+    if (hipHostMalloc((void **)&c->hcnt, sizeof(Counters), hipHostMallocDefault) != hipSuccess)
+        return bail(fail(SRM_ENOMEM, "pinned allocation failed"));
+
+    // Upload in id order into T, then bin into P (committed state).
+    const hipMemcpyKind kind = (mem_kind == SRM_MEM_HOST) ? hipMemcpyHostToDevice
+                                                          : hipMemcpyDeviceToDevice;
+    for (int a = 0; a < c->dim; ++a)
+        if (hipMemcpyAsync(c->T.x[a], pos + (size_t)a * n, n * sizeof(double), kind, c->stream))
+            return bail(fail(SRM_EDEVICE, "position upload failed"));
+    if (c->poly && hipMemcpyAsync(c->T.rho, rho, n * sizeof(double), kind, c->stream))
+        return bail(fail(SRM_EDEVICE, "rho upload failed"));
+    if (c->plate)
+        for (int a = 0; a < 3; ++a)
+            if (hipMemcpyAsync(c->T.nrm[a], normals + (size_t)a * n, n * sizeof(double), kind,
+                               c->stream))
+                return bail(fail(SRM_EDEVICE, "normal upload failed"));
+    if (launch_iota(c->T.id, c->n, c->stream) != hipSuccess)
+        return bail(fail(SRM_EDEVICE, "id init failed"));
+
+    // rho_max and sum rho^dim on the host (order: ascending id).
+    if (c->poly) {
+        double *h = (double *)malloc(n * sizeof(double));
+        if (!h) return bail(fail(SRM_ENOMEM, "host allocation failed"));
+        if (hipMemcpyAsync(h, c->T.rho, n * sizeof(double), hipMemcpyDeviceToHost, c->stream) ||
+            hipStreamSynchronize(c->stream)) {
+            free(h);
+            return bail(fail(SRM_EDEVICE, "rho readback failed"));
+        }
+        double m = 0.0, sd = 0.0;
+        bool ok = true;
+        for (size_t i = 0; i < n; ++i) {
+            if (!(h[i] > 0.0) || !isfinite(h[i])) ok = false;
+            if (h[i] > m) m = h[i];
+            double v = 1.0;
+            for (int a = 0; a < c->dim; ++a) v *= h[i];
+            sd += v;
+        }
+        free(h);
+        if (!ok) return bail(fail(SRM_EINVAL, "rho must be finite and > 0"));
+        c->rho_max = m;
+        c->sum_rho_d = sd;
+    } else {
+        c->rho_max = 1.0;
+        c->sum_rho_d = (double)c->n;
+    }
+
+    // Validation: every coordinate in [0, L) (recorded by the binning
+    // kernel), then no overlapping pair at s0.
+    const Grid g = make_grid(c, c->s * c->rho_max);
+    if (launch_zero_counters(c->dcnt, c->stream) != hipSuccess)
+        return bail(fail(SRM_EDEVICE, "counter init failed"));
+    if ((st = bin(c, c->T, c->P, g))) return bail(st);
+    if (hipMemcpyAsync(c->hcnt, c->dcnt, sizeof(Counters), hipMemcpyDeviceToHost, c->stream) ||
+        hipStreamSynchronize(c->stream))
+        return bail(fail(SRM_EDEVICE, "initial binning failed"));
+    if (c->hcnt->bad) return bail(fail(SRM_EINVAL, "a coordinate is outside [0, L) or NaN"));
+    PassArgs a = pass_args(c, c->P, g, c->s, 0, 0);
+    if (check_overlaps(c->dim, c->p.shape, c->poly, a, true, c->dcnt, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->hcnt, c->dcnt, sizeof(Counters), hipMemcpyDeviceToHost, c->stream) ||
+        hipStreamSynchronize(c->stream))
+        return bail(fail(SRM_EDEVICE, "initial check failed"));
+    if (c->hcnt->overlap) return bail(fail(SRM_EOVERLAP, "initial configuration overlaps at s0"));
+    *out = c;
+    return SRM_OK;
+}
+
+srm_status srm_free(srm_ctx *c)
+{
+    if (!c) return SRM_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    delete c;
+    return SRM_OK;
+}
+
+srm_status srm_sweep(srm_ctx *c, srm_sweep_info *info)
+{
+    if (!c) return fail(SRM_EINVAL, "ctx is NULL");
+    const double s1 = swell(c, c->s);
+    const Grid g = make_grid(c, s1 * c->rho_max);
+    srm_status st;
+    // Q = P, binned for the new grid.
+    if ((st = bin(c, c->P, c->Q, g))) return st;
+    bool committed = false;
+    int32_t passes_main = 0, passes_shake = 0;
+    int64_t nfail = 0;
+    for (int32_t k = 1; k <= c->p.n_k; ++k) {
+        if (k > 1) {
+            if ((st = bin(c, c->Q, c->T, g))) return st;
+            std::swap(c->Q, c->T);
+        }
+        int32_t ov = 1;
+        if ((st = run_pass(c, c->Q, g, s1, SRM_PASS_MAIN, k, true, &ov, &nfail))) return st;
+        ++passes_main;
+        if (!ov) {
+            committed = true;
+            break;
+        }
+    }
+    if (committed) {
+        std::swap(c->P, c->Q);
+        c->s = s1;
+    } else {
+        for (int32_t j = 1; j <= c->p.n_k; ++j) {
+            if ((st = bin(c, c->P, c->T, g))) return st;
+            std::swap(c->P, c->T);
+            if ((st = run_pass(c, c->P, g, c->s, SRM_PASS_SHAKE, j, false, nullptr, nullptr)))
+                return st;
+            ++passes_shake;
+        }
+        if (passes_shake > 0) HIP_TRY(hipStreamSynchronize(c->stream));
+        c->resolve();
+    }
+    c->t += 1;
+    if (info) {
+        info->committed = committed ? 1 : 0;
+        info->passes_main = passes_main;
+        info->passes_shake = passes_shake;
+        for (int a = 0; a < 3; ++a) info->grid[a] = g.na[a];
+        info->sweep = c->t;
+        info->s = c->s;
+        info->fraction = fraction_at(c, c->s);
+        info->n_failed_last = nfail;
+    }
+    return SRM_OK;
+}
+
+srm_status srm_run_to_fraction(srm_ctx *c, int32_t max_sweeps, srm_run_info *info)
+{
+    if (!c) return fail(SRM_EINVAL, "ctx is NULL");
+    if (max_sweeps < 0) return fail(SRM_EINVAL, "max_sweeps < 0");
+    int64_t sweeps = 0, passes = 0, shakes = 0;
+    srm_status st = SRM_OK;
+    while (c->s < c->p.s_target) {
+        if (sweeps >= max_sweeps) {
+            st = fail(SRM_ENOTCONV, "no convergence in %d sweeps", max_sweeps);
+            break;
+        }
+        srm_sweep_info si;
+        srm_status e = srm_sweep(c, &si);
+        if (e) return e;
+        ++sweeps;
+        passes += si.passes_main + si.passes_shake;
+        shakes += si.committed ? 0 : 1;
+    }
+    if (info) {
+        info->sweeps = sweeps;
+        info->passes = passes;
+        info->shakes = shakes;
+        info->updates = passes * (int64_t)c->n;
+        info->s = c->s;
+        info->fraction = fraction_at(c, c->s);
+    }
+    return st;
+}
+
+srm_status srm_get_state(srm_ctx *c, double *pos, double *normals, double *s, int64_t *sweep,
+                         int32_t mem_kind)
+{
+    if (!c) return fail(SRM_EINVAL, "ctx is NULL");
+    if (mem_kind != SRM_MEM_HOST && mem_kind != SRM_MEM_DEVICE)
+        return fail(SRM_EINVAL, "bad mem_kind");
+    if (normals && !c->plate) return fail(SRM_EINVAL, "no normals in a ball system");
+    const size_t n = (size_t)c->n;
+    const hipMemcpyKind kind = (mem_kind == SRM_MEM_HOST) ? hipMemcpyDeviceToHost
+                                                          : hipMemcpyDeviceToDevice;
+    if (pos) {
+        const double *xs[3] = {c->P.x[0], c->P.x[1], c->P.x[2]};
+        HIP_TRY(to_id_order(xs, c->dim, c->P.id, c->n, c->dtmp, c->stream));
+        HIP_TRY(hipMemcpyAsync(pos, c->dtmp, (size_t)c->dim * n * sizeof(double), kind,
+                               c->stream));
+    }
+    if (normals) {
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        const double *ns[3] = {c->P.nrm[0], c->P.nrm[1], c->P.nrm[2]};
+        HIP_TRY(to_id_order(ns, 3, c->P.id, c->n, c->dtmp, c->stream));
+        HIP_TRY(hipMemcpyAsync(normals, c->dtmp, 3 * n * sizeof(double), kind, c->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (s) *s = c->s;
+    if (sweep) *sweep = c->t;
+    return SRM_OK;
+}
+
+srm_status srm_grid(srm_ctx *c, double s, int32_t na[3])
+{
+    if (!c || !na) return fail(SRM_EINVAL, "NULL argument");
+    const Grid g = make_grid(c, s * c->rho_max);
+    for (int a = 0; a < 3; ++a) na[a] = g.na[a];
+    return SRM_OK;
+}
+
+srm_status srm_cells(srm_ctx *c, double grid_s, int32_t *cell_by_id)
+{
+    if (!c || !cell_by_id) return fail(SRM_EINVAL, "NULL argument");
+    const Grid g = make_grid(c, grid_s * c->rho_max);
+    HIP_TRY(cells_by_id(c->dim, c->P, c->n, g, c->itmp, c->stream));
+    HIP_TRY(hipMemcpyAsync(cell_by_id, c->itmp, (size_t)c->n * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SRM_OK;
+}
+
+srm_status srm_pass(srm_ctx *c, double grid_s, double radius_s, int32_t kind, int32_t k,
+                    uint8_t *acc_by_id, int32_t *overlap)
+{
+    if (!c) return fail(SRM_EINVAL, "ctx is NULL");
+    if (kind != SRM_PASS_MAIN && kind != SRM_PASS_SHAKE) return fail(SRM_EINVAL, "bad kind");
+    if (k < 0 || k > 65535) return fail(SRM_EINVAL, "k out of range");
+    const Grid g = make_grid(c, grid_s * c->rho_max);
+    srm_status st;
+    if ((st = bin(c, c->P, c->T, g))) return st;
+    std::swap(c->P, c->T);
+    int32_t ov = 0;
+    if ((st = run_pass(c, c->P, g, radius_s, kind, k, true, &ov, nullptr))) return st;
+    if (overlap) *overlap = ov;
+    if (acc_by_id) return srm_last_acc(c, acc_by_id);
+    return SRM_OK;
+}
+
+srm_status srm_last_acc(srm_ctx *c, uint8_t *acc_by_id)
+{
+    if (!c || !acc_by_id) return fail(SRM_EINVAL, "NULL argument");
+    if (!c->acc_valid) return fail(SRM_EINVAL, "no pass has run");
+    uint8_t *tmp = (uint8_t *)c->itmp;
+    HIP_TRY(u8_to_id_order(c->acc, c->acc_buf.id, c->n, tmp, c->stream));
+    HIP_TRY(hipMemcpyAsync(acc_by_id, tmp, (size_t)c->n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SRM_OK;
+}
+
+srm_status srm_pairs(srm_ctx *c, double gap, int64_t cap, int32_t *ij, int64_t *count,
+                     int32_t mem_kind)
+{
+    (void)gap; (void)cap; (void)ij; (void)mem_kind;
+    if (!c || !count) return fail(SRM_EINVAL, "NULL argument");
+    return fail(SRM_EINVAL, "srm_pairs: not built yet");
+}
+
+srm_status srm_rdf(srm_ctx *c, int32_t nbins, double r_max, uint64_t *counts, double *g)
+{
+    (void)nbins; (void)r_max; (void)counts; (void)g;
+    if (!c) return fail(SRM_EINVAL, "ctx is NULL");
+    return fail(SRM_EINVAL, "srm_rdf: not built yet");
+}
+
+srm_status srm_profile_enable(srm_ctx *c, int32_t on)
+{
+    if (!c) return fail(SRM_EINVAL, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->resolve();
+    c->prof = srm_profile{};
+    c->prof_on = on != 0;
+    return SRM_OK;
+}
+
+srm_status srm_profile_read(srm_ctx *c, srm_profile *out)
+{
+    if (!c || !out) return fail(SRM_EINVAL, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->resolve();
+    *out = c->prof;
+    return SRM_OK;
+}
+
+namespace {
+
+// Device staging for the diagnostics: copy host inputs in, run, copy out.
+struct DevArena {
+    void *p[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~DevArena()
+    {
+        for (void *q : p)
+            if (q) (void)hipFree(q);
+    }
+};
+
+}  // namespace
+
+srm_status srm_debug_fp(const double *a, const double *b, int64_t n, double *sqrt_out,
+                        double *div_out)
+{
+    if (n < 0 || n > 0x7fffffffLL || (n > 0 && (!a || !b || !sqrt_out || !div_out)))
+        return fail(SRM_EINVAL, "bad arguments");
+    if (n == 0) return SRM_OK;
+    DevArena d;
+    const size_t bytes = (size_t)n * sizeof(double);
+    for (int i = 0; i < 4; ++i) HIP_TRY(hipMalloc(&d.p[i], bytes));
+    HIP_TRY(hipMemcpy(d.p[0], a, bytes, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.p[1], b, bytes, hipMemcpyHostToDevice));
+    HIP_TRY(diag_fp((double *)d.p[0], (double *)d.p[1], (int32_t)n, (double *)d.p[2],
+                    (double *)d.p[3], nullptr));
+    HIP_TRY(hipMemcpy(sqrt_out, d.p[2], bytes, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(div_out, d.p[3], bytes, hipMemcpyDeviceToHost));
+    return SRM_OK;
+}
+
+srm_status srm_debug_philox(const uint64_t *ctr, const uint64_t *key, int64_t n, uint64_t *out)
+{
+    if (n < 0 || n > 0x0fffffffLL || (n > 0 && (!ctr || !key || !out)))
+        return fail(SRM_EINVAL, "bad arguments");
+    if (n == 0) return SRM_OK;
+    DevArena d;
+    HIP_TRY(hipMalloc(&d.p[0], (size_t)n * 32));
+    HIP_TRY(hipMalloc(&d.p[1], (size_t)n * 16));
+    HIP_TRY(hipMalloc(&d.p[2], (size_t)n * 32));
+    HIP_TRY(hipMemcpy(d.p[0], ctr, (size_t)n * 32, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.p[1], key, (size_t)n * 16, hipMemcpyHostToDevice));
+    HIP_TRY(diag_philox((const uint64_t *)d.p[0], (const uint64_t *)d.p[1], (int32_t)n,
+                        (uint64_t *)d.p[2], nullptr));
+    HIP_TRY(hipMemcpy(out, d.p[2], (size_t)n * 32, hipMemcpyDeviceToHost));
+    return SRM_OK;
+}
+
+srm_status srm_debug_unitvec(int32_t dim, uint64_t seed, uint64_t t, uint64_t kkl,
+                             uint64_t stream, double len, int64_t n, double *out)
+{
+    if ((dim != 2 && dim != 3) || n < 0 || n > 0x0fffffffLL || (n > 0 && !out))
+        return fail(SRM_EINVAL, "bad arguments");
+    if (n == 0) return SRM_OK;
+    DevArena d;
+    HIP_TRY(hipMalloc(&d.p[0], (size_t)n * 24));
+    HIP_TRY(diag_unitvec(dim, seed, t, kkl, stream, len, (int32_t)n, (double *)d.p[0], nullptr));
+    HIP_TRY(hipMemcpy(out, d.p[0], (size_t)n * 24, hipMemcpyDeviceToHost));
+    return SRM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// srm_device.hpp -- device-side building blocks of the SRM sweep on gfx950:
+// counter-based random numbers, the random unit vector of Algorithm 3,
+// periodic wrap (Algorithm 4), minimum image (Algorithm 5), cell coordinates
+// (Algorithm 2) and the thin-disk intersection predicate (Sec. 3.3).
+//
+// Every expression is written so that, compiled with -ffp-contract=off,
+// it performs exactly the IEEE binary64 operations of the method's
+// definition in the same order (no fused multiply-add), so results agree bit
+// for bit with any other correctly rounded evaluation of the same sequence.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace srm {
+
+constexpr int kMaxDim = 3;
+
+// Adaptive cell grid of one sweep (cells per axis, reciprocal width, box).
+struct Grid {
+    int32_t na[3];
+    int32_t ncell;
+    double inv_w[3];
+    double box[3];
+    double half[3];  // 0.5 * box[a], exact
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the
+// 4-word multiply/xor bijection with a Weyl-sequence key schedule.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64_10(uint64_t &x0, uint64_t &x1, uint64_t &x2,
+                                              uint64_t &x3, uint64_t k0, uint64_t k1)
+{
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t lo0 = M0 * x0, hi0 = __umul64hi(M0, x0);
+        const uint64_t lo1 = M1 * x2, hi1 = __umul64hi(M1, x2);
+        const uint64_t y0 = hi1 ^ x1 ^ k0;
+        const uint64_t y2 = hi0 ^ x3 ^ k1;
+        x0 = y0;
+        x1 = lo1;
+        x2 = y2;
+        x3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+}
+
+// Random vector of length `len` with uniform direction: Philox words
+// mapped to w_a = 2 u_a - 1 (u_a = (W_a >> 11) 2^-53, exact), rejected
+// unless 0 < |w|^2 <= 1, then scaled by len / sqrt(|w|^2).  Counter
+// (id, t, kind<<48 | k<<32 | l<<16 | round, stream), key (seed, 0).
+template <int DIM>
+__device__ __forceinline__ void unit_vector(uint64_t seed, uint64_t id, uint64_t t,
+                                            uint64_t kkl, uint64_t stream, double len,
+                                            double v[3])
+{
+    for (uint32_t r = 0; r < 64; ++r) {
+        uint64_t x0 = id, x1 = t, x2 = kkl | (uint64_t)r, x3 = stream;
+        philox4x64_10(x0, x1, x2, x3, seed, 0);
+        const double w0 = 2.0 * ((double)(x0 >> 11) * 0x1p-53) - 1.0;
+        const double w1 = 2.0 * ((double)(x1 >> 11) * 0x1p-53) - 1.0;
+        const double w2 = 2.0 * ((double)(x2 >> 11) * 0x1p-53) - 1.0;
+        double q = w0 * w0 + w1 * w1;
+        if (DIM == 3) q = q + w2 * w2;
+        if (q > 0.0 && q <= 1.0) {
+            const double g = len / __builtin_sqrt(q);
+            v[0] = w0 * g;
+            v[1] = w1 * g;
+            v[2] = (DIM == 3) ? w2 * g : 0.0;
+            return;
+        }
+    }
+    v[0] = len;
+    v[1] = 0.0;
+    v[2] = 0.0;
+}
+
+__device__ __forceinline__ uint64_t counter_word(uint32_t kind, uint32_t k, uint32_t l)
+{
+    return ((uint64_t)kind << 48) | ((uint64_t)k << 32) | ((uint64_t)l << 16);
+}
+
+// Algorithm 4: if x < 0 add L, then if x >= L subtract L.
+__device__ __forceinline__ double wrap_coord(double x, double L)
+{
+    if (x < 0.0) x += L;
+    if (x >= L) x -= L;
+    return x;
+}
+
+// Minimum image of Algorithm 5 on one axis (half = 0.5 L).
+__device__ __forceinline__ double min_image(double d, double L, double half)
+{
+    if (d > half) d -= L;
+    if (d < -half) d += L;
+    return d;
+}
+
+// Algorithm 2 cell coordinate: (int)(x * N_a / L_a); the top edge folds to 0.
+__device__ __forceinline__ int32_t cell_coord(double x, double inv_w, int32_t na)
+{
+    int32_t c = (int32_t)(x * inv_w);
+    return (c == na) ? 0 : c;
+}
+
+template <int DIM>
+__device__ __forceinline__ int32_t cell_of(const Grid &g, double x, double y, double z)
+{
+    const int32_t cx = cell_coord(x, g.inv_w[0], g.na[0]);
+    const int32_t cy = cell_coord(y, g.inv_w[1], g.na[1]);
+    const int32_t cz = (DIM == 3) ? cell_coord(z, g.inv_w[2], g.na[2]) : 0;
+    return cx + g.na[0] * (cy + g.na[1] * cz);
+}
+
+// Zero-thickness disk-disk intersection: (c1, n1, a1) is the disk with the
+// lower particle id.  d = minimum image of c2 - c1.  Cull on |d| > a1 + a2;
+// parallel planes intersect only when coplanar; otherwise both disks must
+// reach the planes' common line and their chords on it must overlap.
+__device__ __forceinline__ bool disks_intersect(double dx, double dy, double dz,
+                                                const double n1[3], double a1,
+                                                const double n2[3], double a2)
+{
+    const double dd = dx * dx + dy * dy + dz * dz;
+    const double sa = a1 + a2;
+    if (dd > sa * sa) return false;
+    const double ux = n1[1] * n2[2] - n1[2] * n2[1];
+    const double uy = n1[2] * n2[0] - n1[0] * n2[2];
+    const double uz = n1[0] * n2[1] - n1[1] * n2[0];
+    const double uu = ux * ux + uy * uy + uz * uz;
+    if (uu == 0.0) {
+        const double hn = n1[0] * dx + n1[1] * dy + n1[2] * dz;
+        return hn == 0.0;
+    }
+    const double h = n2[0] * dx + n2[1] * dy + n2[2] * dz;
+    const double wx = uy * n1[2] - uz * n1[1];
+    const double wy = uz * n1[0] - ux * n1[2];
+    const double wz = ux * n1[1] - uy * n1[0];
+    const double f = h / uu;
+    const double px = wx * f, py = wy * f, pz = wz * f;
+    const double A = a1 * a1 - (px * px + py * py + pz * pz);
+    if (A < 0.0) return false;
+    const double ex = dx - px, ey = dy - py, ez = dz - pz;
+    const double t0 = (ex * ux + ey * uy + ez * uz) / uu;
+    const double B = a2 * a2 - ((ex * ex + ey * ey + ez * ez) - (t0 * t0) * uu);
+    if (B < 0.0) return false;
+    const double Ap = A / uu, Bp = B / uu, C = t0 * t0;
+    const double D = (C - Ap) - Bp;
+    if (D <= 0.0) return true;
+    return D * D <= (4.0 * Ap) * Bp;
+}
+
+}  // namespace srm

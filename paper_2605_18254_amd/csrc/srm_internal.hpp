@@ -1,0 +1,98 @@
+// srm_internal.hpp -- context layout and the host launchers shared by the
+// translation units of libsrm (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "srm.h"
+#include "srm_device.hpp"
+
+namespace srm {
+
+// Particle arrays of one storage order (cells ascending, ids ascending
+// within a cell after a rebin).  Unused arrays are null.
+struct PBuf {
+    double *x[3];
+    double *nrm[3];
+    double *rho;
+    int32_t *id;
+};
+
+// Small device-side result block of the global check.
+struct Counters {
+    int32_t overlap;   // 1 if a colliding particle was found
+    int32_t bad;       // 1 if an input coordinate was outside the box
+    int64_t nfail;     // particles with accept code 0
+};
+
+struct Scratch {
+    int32_t *cell;      // [n] destination cell per source slot
+    int32_t *slot;      // [n] rank within the destination cell (atomic order)
+    int32_t *counts;    // [cap] particles per cell
+    int32_t *start;     // [cap + 1] exclusive prefix of counts
+    int32_t *partials;  // per-block sums of the scan
+    int64_t cap;        // cell capacity (>= every grid's ncell)
+};
+
+// Launch configuration of one migration colour phase.
+struct ColourLattice {
+    int32_t h[3];   // colour cells per axis
+    int32_t off[3]; // parity offset per axis
+    int32_t count;  // colour cells in this phase
+};
+
+// Host launchers (all enqueue on `stream`).
+hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t stream);
+hipError_t launch_fill_u8(uint8_t *a, int64_t n, uint8_t v, hipStream_t stream);
+hipError_t launch_zero_counters(Counters *c, hipStream_t stream);
+hipError_t launch_iota(int32_t *a, int32_t n, hipStream_t stream);
+
+// Counting sort of `src` by the cells of `g` into `dst` (Algorithm 2's
+// lists as a cell-sorted CSR array `sc.start`, ids ascending within a cell).
+hipError_t bin_particles(int dim, const PBuf &src, const PBuf &dst, int32_t n, const Grid &g,
+                         Scratch &sc, Counters *cnt, hipStream_t stream);
+// Exclusive scan of counts[0..m) into start[0..m] (start[m] = total).
+hipError_t scan_counts(const int32_t *counts, int32_t *start, int32_t *partials, int32_t m,
+                       hipStream_t stream);
+// Scatter sorted-order arrays to particle-id order: out[a*n + id[p]] = x[a][p].
+hipError_t to_id_order(const double *const *x, int nx, const int32_t *id, int32_t n, double *out,
+                       hipStream_t stream);
+hipError_t u8_to_id_order(const uint8_t *a, const int32_t *id, int32_t n, uint8_t *out,
+                          hipStream_t stream);
+hipError_t cells_by_id(int dim, const PBuf &b, int32_t n, const Grid &g, int32_t *out,
+                       hipStream_t stream);
+
+struct PassArgs {
+    PBuf buf;
+    const int32_t *start;
+    uint8_t *acc;
+    Grid g;
+    int32_t n;
+    double s;          // radius scale of this pass
+    double sig2_mono;  // (s + s)^2 for monodisperse balls
+    uint64_t seed;
+    uint64_t t;
+    uint64_t kk;       // kind<<48 | k<<32
+    int32_t n_l;
+    double c_m, c_n;
+};
+
+// One colour phase of a migration pass (Algorithm 3 over the cells whose
+// parity vector is `colour`); *launched is false for an empty phase.
+hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int colour,
+                          hipStream_t stream, bool *launched);
+// Global check (Algorithm 6) restricted to particles with accept code 0
+// (or every particle when check_all), result into cnt.
+hipError_t check_overlaps(int dim, int shape, bool poly, const PassArgs &a, bool check_all,
+                          Counters *cnt, hipStream_t stream);
+
+// Diagnostics of the device arithmetic (k_diag.hip).
+hipError_t diag_fp(const double *a, const double *b, int32_t n, double *sq, double *dv,
+                   hipStream_t s);
+hipError_t diag_philox(const uint64_t *ctr, const uint64_t *key, int32_t n, uint64_t *out,
+                       hipStream_t s);
+hipError_t diag_unitvec(int dim, uint64_t seed, uint64_t t, uint64_t kkl, uint64_t stream,
+                        double len, int32_t n, double *out, hipStream_t s);
+
+}  // namespace srm

@@ -1,0 +1,311 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+The contract is bit-exactness: cell assignment, accept codes, the overlap
+flag and every FP64 coordinate must be identical (both sides evaluate the
+same IEEE binary64 operation sequence without contraction).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import srm_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def srm():
+    import paper_2605_18254_amd as m
+    m.lib()
+    return m
+
+
+def _mk(dim, n, seed, f=0.3, **kw):
+    return srm_inputs.make("disks2d" if dim == 2 else "spheres3d", n=n, seed=seed, f_target=f,
+                           **kw)
+
+
+def _gpu_from_oracle(srm, o, w, **over):
+    kw = dict(pos=o.soa(), s0=o.s, sweep0=o.t)
+    if o.nrm is not None:
+        kw["normals"] = np.ascontiguousarray(o.nrm.T)
+    kw.update(over)
+    return srm.SRM.from_workload(w, **kw)
+
+
+def _assert_same_state(g, o, where=""):
+    pos, nrm, s, t = g.state()
+    ref = o.soa()
+    if not np.array_equal(pos, ref):
+        bad = np.nonzero(np.any(pos != ref, axis=0))[0]
+        raise AssertionError(f"{where}: {len(bad)} positions differ, first ids {bad[:8]}")
+    if o.nrm is not None:
+        assert np.array_equal(nrm, np.ascontiguousarray(o.nrm.T)), where
+    assert s == o.s and t == o.t, (where, s, o.s, t, o.t)
+
+
+# ------------------------------------------------------------ device arithmetic
+
+def test_device_sqrt_and_division_correctly_rounded(srm):
+    rng = np.random.default_rng(0)
+    n = 1_000_000
+    a = np.concatenate([rng.random(n // 2), np.exp(rng.uniform(-700, 700, n // 2)),
+                        [0.0, 1.0, 4.0, 2.0, 1e-310, 5e-324, 1.7976931348623157e308]])
+    b = np.concatenate([rng.random(n // 2) + 1e-3, np.exp(rng.uniform(-300, 300, n // 2)),
+                        [1.0, 3.0, 7.0, 0.1, 3.0, 2.0, 0.5]])
+    sq, dv = srm.debug_fp(a, b)
+    assert np.array_equal(sq, np.sqrt(a))
+    assert np.array_equal(dv, a / b)
+    # the values the unit-vector draw actually sees: q in (0, 1]
+    q = rng.random(n) + 2.0**-53
+    sq, dv = srm.debug_fp(q, np.sqrt(q))
+    assert np.array_equal(sq, np.sqrt(q))
+    assert np.array_equal(dv, q / np.sqrt(q))
+
+
+def test_device_philox_matches_numpy(srm):
+    rng = np.random.default_rng(1)
+    n = 20000
+    ctr = rng.integers(0, 2**63, size=(n, 4), dtype=np.int64).astype(np.uint64) * np.uint64(2)
+    ctr += rng.integers(0, 2, size=(n, 4)).astype(np.uint64)
+    key = rng.integers(0, 2**63, size=(n, 2), dtype=np.int64).astype(np.uint64)
+    out = srm.debug_philox(ctr, key)
+    for i in range(0, n, 97):
+        c = [int(x) for x in ctr[i]]
+        cint = c[0] | (c[1] << 64) | (c[2] << 128) | (c[3] << 192)
+        bg = np.random.Philox(key=int(key[i, 0]) | (int(key[i, 1]) << 64),
+                              counter=(cint - 1) % (1 << 256))
+        assert np.array_equal(bg.random_raw(4), out[i])
+
+
+@pytest.mark.parametrize("dim,stream", [(2, 0), (3, 0), (3, 1)])
+def test_device_unitvec_matches_oracle(srm, oracle_lib, dim, stream):
+    n = 3000
+    dev = srm.debug_unitvec(dim, 99, 17, 1, 5, 3, stream, 2.5e-3, n)
+    for i in range(n):
+        v, _ = oracle_lib.unitvec(dim, 99, i, 17, 1, 5, 3, stream, 2.5e-3)
+        assert np.array_equal(v, dev[i]), i
+
+
+# ------------------------------------------------------------------- binning
+
+@pytest.mark.parametrize("dim,n,f", [(2, 2000, 0.5), (3, 20000, 0.35), (3, 4097, 0.3),
+                                     (2, 7, 0.3), (3, 1, 0.1)])
+def test_cell_assignment_parity(srm, oracle_lib, dim, n, f):
+    w = _mk(dim, n, 5 + n % 7, f)
+    o = oracle_lib.Oracle.from_workload(w)
+    g = srm.SRM.from_workload(w)
+    for s in (0.0, 0.3 * w.s_target, w.s_target):
+        na, inv = o.grid_for_scale(s)
+        assert tuple(int(x) for x in na) == g.grid(s)
+        assert np.array_equal(g.cells(s).astype(np.int64), o.bin(na, inv))
+    g.close()
+
+
+# -------------------------------------------------------------- single pass
+
+@pytest.mark.parametrize("dim,n,f,kind", [(2, 2000, 0.5, 0), (3, 20000, 0.35, 0),
+                                          (3, 5000, 0.45, 1), (2, 333, 0.6, 0),
+                                          (3, 600, 0.2, 0)])
+def test_single_pass_parity(srm, oracle_lib, dim, n, f, kind):
+    w = _mk(dim, n, 60 + n % 11, f)
+    o = oracle_lib.Oracle.from_workload(w)
+    o.run(5000)
+    o.t = 424242
+    g = _gpu_from_oracle(srm, o, w)
+    for k, grow in [(1, 1.0), (2, 1.02), (3, 1.05)]:
+        s = o.s * grow
+        na, inv = o.grid_for_scale(s)
+        acc_o, ov_o = o.pass_(na, inv, s, kind, k)
+        acc_g, ov_g = g.pass_(s, s, kind, k)
+        _say(f"pass dim={dim} n={n} k={k}: accepted {int((acc_o > 0).sum())}, overlap {ov_o}")
+        assert np.array_equal(acc_g, acc_o), np.nonzero(acc_g != acc_o)[0][:10]
+        assert ov_g == ov_o
+        _assert_same_state(g, o, f"pass k={k}")
+    g.close()
+
+
+# ------------------------------------------------------------------- sweeps
+
+def _sweep_parity(srm, oracle_lib, w, max_sweeps, every=1, **over):
+    o = oracle_lib.Oracle.from_workload(w, **over)
+    g = srm.SRM.from_workload(w, **over)
+    sweeps = 0
+    while o.s < w.s_target and sweeps < max_sweeps:
+        io, acc_o = o.sweep()
+        ig = g.sweep()
+        sweeps += 1
+        assert ig["committed"] == io["committed"], sweeps
+        assert ig["passes_main"] == io["passes_main"], sweeps
+        assert ig["passes_shake"] == io["passes_shake"], sweeps
+        assert ig["n_failed_last"] == io["n_failed_last"], sweeps
+        assert tuple(ig["grid"]) == tuple(int(x) for x in io["na"]), sweeps
+        assert ig["s"] == o.s and ig["sweep"] == o.t
+        if sweeps % every == 0:
+            assert np.array_equal(g.last_acc(), acc_o), sweeps
+            _assert_same_state(g, o, f"sweep {sweeps}")
+    _assert_same_state(g, o, "final")
+    return o, g, sweeps
+
+
+def test_config1_full_run_bitexact(srm, oracle_lib):
+    """2D, N=2000 disks, f=0.5, seed 0: every sweep bit-identical."""
+    w = srm_inputs.make("disks2d")
+    o, g, sweeps = _sweep_parity(srm, oracle_lib, w, 1000)
+    assert o.s == w.s_target
+    _say(f"config 1: {sweeps} sweeps, fraction {g.sweep()['fraction'] if False else o.fraction()}")
+    g.close()
+
+
+def test_3d_run_bitexact(srm, oracle_lib):
+    w = _mk(3, 20000, 71, 0.35)
+    o, g, sweeps = _sweep_parity(srm, oracle_lib, w, 1000, every=10)
+    assert o.s == w.s_target
+    g.close()
+
+
+def test_polydisperse_run_bitexact(srm, oracle_lib):
+    w = _mk(3, 3000, 72, 0.4, polydisperse_sigma=0.2)
+    o, g, _ = _sweep_parity(srm, oracle_lib, w, 1000, every=5)
+    assert o.s == w.s_target
+    g.close()
+
+
+def test_2d_polydisperse_fast_swell_with_shakes(srm, oracle_lib):
+    """Large swelling steps and few trials: sweeps shake, and the shake
+    branch must match too."""
+    w = _mk(2, 1500, 73, 0.62, polydisperse_sigma=0.2, c_w=0.08, n_k=3, n_l=2)
+    o = oracle_lib.Oracle.from_workload(w)
+    g = srm.SRM.from_workload(w)
+    shakes = 0
+    for sweep in range(60):
+        io, acc_o = o.sweep()
+        ig = g.sweep()
+        shakes += not io["committed"]
+        assert ig["committed"] == io["committed"] and ig["passes_main"] == io["passes_main"]
+        assert np.array_equal(g.last_acc(), acc_o)
+        _assert_same_state(g, o, f"sweep {sweep}")
+    assert shakes > 0
+    g.close()
+
+
+def test_platelets_bitexact(srm, oracle_lib):
+    w = srm_inputs.make("platelets", n=3000, f_target=0.02, cap_deg=15.0)
+    o, g, sweeps = _sweep_parity(srm, oracle_lib, w, 40, every=4)
+    _say(f"platelets: {sweeps} sweeps, s={o.s}")
+    g.close()
+
+
+def test_platelets_isotropic_passes(srm, oracle_lib):
+    w = srm_inputs.make("platelets", n=2500, seed=5, f_target=0.03, c_w=0.05)
+    o, g, sweeps = _sweep_parity(srm, oracle_lib, w, 25, every=1)
+    g.close()
+
+
+# --------------------------------------------------------------- edge cases
+
+def test_single_particle_and_tiny_systems(srm, oracle_lib):
+    for n in (1, 2, 3, 9):
+        w = _mk(3, n, 80 + n, 0.2)
+        o, g, _ = _sweep_parity(srm, oracle_lib, w, 300)
+        assert o.s == w.s_target
+        g.close()
+
+
+def test_zero_trials_and_zero_step(srm, oracle_lib):
+    w = _mk(2, 500, 90, 0.3, n_l=0)
+    o, g, _ = _sweep_parity(srm, oracle_lib, w, 20)
+    g.close()
+    w = _mk(3, 500, 91, 0.3)
+    w.c_m = 0.0
+    o, g, _ = _sweep_parity(srm, oracle_lib, w, 30)
+    g.close()
+
+
+def test_overlapping_start_rejected(srm):
+    w = _mk(2, 100, 92, 0.3)
+    w.pos[:, 1] = w.pos[:, 0]
+    with pytest.raises(srm.SrmError) as e:
+        srm.SRM.from_workload(w, s0=1e-3)
+    assert e.value.status == srm.EOVERLAP
+
+
+def test_out_of_box_rejected(srm):
+    w = _mk(3, 100, 93, 0.3)
+    w.pos[1, 7] = 1.0
+    with pytest.raises(srm.SrmError) as e:
+        srm.SRM.from_workload(w)
+    assert e.value.status == srm.EINVAL
+    w.pos[1, 7] = float("nan")
+    with pytest.raises(srm.SrmError):
+        srm.SRM.from_workload(w)
+
+
+def test_not_converged_keeps_admissible_state(srm, oracle_lib):
+    w = _mk(2, 800, 94, 0.5)
+    g = srm.SRM.from_workload(w)
+    st, info = g.run(7)
+    assert st == srm.ENOTCONV and info["sweeps"] == 7
+    o = oracle_lib.Oracle.from_workload(w)
+    rc, sw, _ = o.run(7)
+    assert rc == oracle_lib.ENOTCONV
+    _assert_same_state(g, o, "after ENOTCONV")
+    assert not o.overlap()
+    g.close()
+
+
+def test_resume_is_bitexact(srm):
+    w = _mk(3, 4000, 95, 0.3)
+    a = srm.SRM.from_workload(w)
+    for _ in range(40):
+        a.sweep()
+    b = srm.SRM.from_workload(w)
+    for _ in range(25):
+        b.sweep()
+    pos, _, s, t = b.state()
+    b.close()
+    c = srm.SRM.from_workload(w, pos=pos, s0=s, sweep0=t)
+    for _ in range(15):
+        c.sweep()
+    pa, _, sa, ta = a.state()
+    pc, _, sc, tc = c.state()
+    assert np.array_equal(pa, pc) and sa == sc and ta == tc
+    a.close()
+    c.close()
+
+
+def test_device_memory_inputs_match_host(srm):
+    import torch
+    w = _mk(3, 5000, 96, 0.3)
+    h = srm.SRM.from_workload(w)
+    d = srm.SRM.from_workload(w, device=True)
+    for _ in range(20):
+        h.sweep()
+        d.sweep()
+    out = torch.empty((3, w.n), dtype=torch.float64, device="cuda")
+    d.state_device(out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), h.state()[0])
+    h.close()
+    d.close()
+
+
+def test_full_run_fraction_and_no_overlap(srm, oracle_lib):
+    """Property at a larger size: the run ends exactly at s_target with the
+    closed-form fraction, and the oracle's global check finds no overlap."""
+    w = _mk(3, 200000, 97, 0.35)
+    g = srm.SRM.from_workload(w)
+    st, info = g.run(2000)
+    assert st == 0 and info["s"] == w.s_target
+    assert abs(info["fraction"] - 0.35) < 1e-12
+    pos, _, s, t = g.state()
+    o = oracle_lib.Oracle.from_workload(w, pos=pos, s0=s, sweep0=t)
+    assert not o.overlap()
+    g.close()
