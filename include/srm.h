@@ -24,10 +24,10 @@
  *    HIP stream given at srm_init (0 = the null stream).  Calls that return
  *    host-visible results synchronise that stream before returning.  A
  *    context is not thread-safe: calls on one context must not overlap.
- *  - Random numbers: Philox4x64-10 with key (seed, 0) and counter
- *    (particle id, sweep, kind<<48 | pass<<32 | trial<<16 | round, stream),
- *    so a run is a pure function of (inputs, params, s0, sweep0): results do
- *    not depend on launch shapes, and a saved state resumes bit-exactly.
+ *  - Random numbers: Philox4x32-10 keyed by the 64-bit seed, counter
+ *    (particle id, sweep, kind<<31 | pass<<16 | trial<<8 | call, stream), so a
+ *    run is a pure function of (inputs, params, s0, sweep0): results do not
+ *    depend on launch shapes, and a saved state resumes bit-exactly.
  */
 #ifndef SRM_H
 #define SRM_H
@@ -69,7 +69,7 @@ typedef struct {
     double c_m;          /* migration step length (absolute) */
     double c_n;          /* platelet normal step (unit-vector length) */
     double thick_ratio;  /* platelet thickness / diameter (volume only) */
-    int32_t n_k;         /* passes per sweep before a shake, 0..65535 */
+    int32_t n_k;         /* passes per sweep before a shake, 0..32767 */
     int32_t n_l;         /* trial moves per particle per pass, 0..255 */
     uint64_t seed;       /* Philox key */
 } srm_params;
@@ -96,7 +96,7 @@ typedef struct {
 /* Create a context.  p: parameters (copied).  pos: dim*n SoA positions in
  * [0, L_a) per axis.  rho: n shape radii > 0, or NULL for all 1.
  * normals: 3*n unit normals (platelets), else NULL.  s0: starting radius
- * scale; sweep0: starting sweep counter (resume).  stream: hipStream_t or
+ * scale; sweep0: starting sweep counter (resume, < 2^32).  stream: hipStream_t or
  * NULL.  Fails with SRM_EOVERLAP if two particles overlap at s0 (Algorithm 1
  * starts from a non-overlapping set), SRM_EINVAL on a bad parameter or a
  * coordinate outside the box.  *out is set only on success. */
@@ -191,15 +191,16 @@ srm_status srm_profile_read(srm_ctx *ctx, srm_profile *out);
 srm_status srm_debug_fp(const double *a, const double *b, int64_t n, double *sqrt_out,
                         double *div_out);
 
-/* Philox4x64-10 on the device: out[4i..4i+3] = philox(ctr[4i..4i+3],
+/* Philox4x32-10 on the device: out[4i..4i+3] = philox(ctr[4i..4i+3],
  * key[2i..2i+1]) for i < n.  Host buffers. */
-srm_status srm_debug_philox(const uint64_t *ctr, const uint64_t *key, int64_t n, uint64_t *out);
+srm_status srm_debug_philox(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32_t *out);
 
 /* The trial-move random vector (length len, dim 2 or 3) drawn on the device
  * for particle ids 0..n-1 with sweep t and counter word
- * kind<<48 | k<<32 | l<<16: out[3i..3i+2] (z = 0 in 2D).  Host buffer. */
-srm_status srm_debug_unitvec(int32_t dim, uint64_t seed, uint64_t t, uint64_t kkl,
-                             uint64_t stream, double len, int64_t n, double *out);
+ * word = kind<<31 | k<<16 | l<<8: out[3i..3i+2] (z = 0 in 2D).  Host
+ * buffer. */
+srm_status srm_debug_unitvec(int32_t dim, uint64_t seed, uint32_t t, uint32_t word,
+                             uint32_t stream, double len, int64_t n, double *out);
 
 #ifdef __cplusplus
 }

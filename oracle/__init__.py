@@ -68,7 +68,7 @@ def lib():
         path = _LIB if os.path.exists(_LIB) else build()
         L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
-        L.o_philox.argtypes = [C.POINTER(C.c_uint64)] * 3
+        L.o_philox4x32.argtypes = [C.POINTER(C.c_uint32)] * 3
         L.o_unitvec.argtypes = [C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
                                 C.c_uint32, C.c_uint32, C.c_uint64, C.c_double, dp]
         L.o_unitvec.restype = C.c_int
@@ -107,12 +107,12 @@ def _dp(a: Optional[np.ndarray]):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def philox(ctr, key) -> np.ndarray:
-    c = (C.c_uint64 * 4)(*[int(x) & (2**64 - 1) for x in ctr])
-    k = (C.c_uint64 * 2)(*[int(x) & (2**64 - 1) for x in key])
-    out = (C.c_uint64 * 4)()
-    lib().o_philox(c, k, out)
-    return np.array(list(out), dtype=np.uint64)
+def philox4x32(ctr, key) -> np.ndarray:
+    c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    out = (C.c_uint32 * 4)()
+    lib().o_philox4x32(c, k, out)
+    return np.array(list(out), dtype=np.uint32)
 
 
 def unitvec(dim, seed, pid, t, kind, k, l, stream, length):

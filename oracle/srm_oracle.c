@@ -31,9 +31,10 @@
  *  - collision test (Alg. 5): cell of the tested position, 3^d neighbour
  *    cells of the current lists, the particle itself excluded, minimum image
  *    per axis, squared form q <= (R_i + R_j)^2 (touching counts as overlap).
- *  - unit random vector (Alg. 3): Philox4x64-10 counter-based draws,
- *    rejection sampling in [-1,1)^d, normalised (no trigonometry); counter
- *    (id, sweep, kind<<48 | k<<32 | l<<16 | round, stream), key (seed, 0).
+ *  - unit random vector (Alg. 3): Philox4x32-10 counter-based draws keyed by
+ *    the seed, counter (id, sweep, kind<<31 | k<<16 | l<<8 | call, stream);
+ *    Marsaglia's rejection method for a uniform point on the sphere (3D) or
+ *    a normalised point of the unit disk (2D); no trigonometry.
  *  - shake (Sec. 2 step d, Alg. 1 else-branch): N_k passes over P at P's
  *    radii, re-binning before each pass; s unchanged.
  *  - the sweep counter t advances after every sweep, committed or shaken.
@@ -95,55 +96,72 @@ typedef struct {
 } o_cells;
 
 /* ------------------------------------------------------------------ */
-/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).                  */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the  */
+/* 4-word multiply/xor bijection with a Weyl key schedule.               */
 /* ------------------------------------------------------------------ */
-void o_philox(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+void o_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
 {
-    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
-    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
-    uint64_t k0 = key[0], k1 = key[1];
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
     for (int round = 0; round < 10; ++round) {
-        unsigned __int128 p0 = (unsigned __int128)M0 * x0;
-        unsigned __int128 p1 = (unsigned __int128)M1 * x2;
-        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
-        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
-        uint64_t y0 = hi1 ^ x1 ^ k0;
-        uint64_t y1 = lo1;
-        uint64_t y2 = hi0 ^ x3 ^ k1;
-        uint64_t y3 = lo0;
+        uint64_t p0 = (uint64_t)M0 * x0;
+        uint64_t p1 = (uint64_t)M1 * x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
         x0 = y0; x1 = y1; x2 = y2; x3 = y3;
         k0 += W0; k1 += W1;
     }
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-/* Unit random vector times `len` (Alg. 3, "c_m * Unit Random Vector").
- * Returns the number of Philox rounds used (65 = fallback). */
+/* 32-bit word -> the odd multiple of 2^-32 in (-1, 1): (w - (2^31 - 1/2)) 2^-31
+ * (every step exact). */
+static double o_sym_uniform(uint32_t w)
+{
+    return ((double)w - 2147483647.5) * 0x1p-31;
+}
+
+/* Random vector of length `len` with uniform direction (Alg. 3, "c_m * Unit
+ * Random Vector").  Each Philox call (counter (id, t, kind<<31 | k<<16 |
+ * l<<8 | call, stream), key (seed_lo, seed_hi)) gives two attempts (v1, v2)
+ * uniform in (-1,1)^2, kept when s = v1^2 + v2^2 < 1.  3D: Marsaglia's
+ * point on the sphere (2 v1 sqrt(1-s), 2 v2 sqrt(1-s), 1 - 2s); 2D:
+ * (v1, v2) / sqrt(s).  Returns the number of calls used (65 = fallback). */
 int o_unitvec(int dim, uint64_t seed, uint64_t id, uint64_t t, uint32_t kind,
               uint32_t k, uint32_t l, uint64_t stream, double len, double v[3])
 {
-    const uint64_t key[2] = {seed, 0};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     for (uint32_t r = 0; r < 64; ++r) {
-        uint64_t ctr[4], W[4];
-        ctr[0] = id;
-        ctr[1] = t;
-        ctr[2] = ((uint64_t)kind << 48) | ((uint64_t)k << 32) | ((uint64_t)l << 16) | (uint64_t)r;
-        ctr[3] = stream;
-        o_philox(ctr, key, W);
-        double w[3];
-        for (int a = 0; a < 3; ++a) {
-            double u = (double)(W[a] >> 11) * 0x1p-53;
-            w[a] = 2.0 * u - 1.0;
-        }
-        double q = w[0] * w[0] + w[1] * w[1];
-        if (dim == 3) q = q + w[2] * w[2];
-        if (q > 0.0 && q <= 1.0) {
-            double g = len / sqrt(q);
-            v[0] = w[0] * g;
-            v[1] = w[1] * g;
-            v[2] = (dim == 3) ? w[2] * g : 0.0;
-            return (int)r + 1;
+        uint32_t ctr[4], W[4];
+        ctr[0] = (uint32_t)id;
+        ctr[1] = (uint32_t)t;
+        ctr[2] = (kind << 31) | (k << 16) | (l << 8) | r;
+        ctr[3] = (uint32_t)stream;
+        o_philox4x32(ctr, key, W);
+        for (int a = 0; a < 2; ++a) {
+            double v1 = o_sym_uniform(W[2 * a]);
+            double v2 = o_sym_uniform(W[2 * a + 1]);
+            double s = v1 * v1 + v2 * v2;
+            if (s < 1.0) {
+                if (dim == 3) {
+                    double h = 2.0 * sqrt(1.0 - s);
+                    v[0] = (v1 * h) * len;
+                    v[1] = (v2 * h) * len;
+                    v[2] = (1.0 - 2.0 * s) * len;
+                } else {
+                    double g = len / sqrt(s);
+                    v[0] = v1 * g;
+                    v[1] = v2 * g;
+                    v[2] = 0.0;
+                }
+                return (int)r + 1;
+            }
         }
     }
     v[0] = len; v[1] = 0.0; v[2] = 0.0;

@@ -71,6 +71,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2605_18254_amd/build.py "
                           "(there is no CPU fallback)")
+    # One HIP runtime per process: when torch is installed its bundled
+    # libamdhip64 is loaded first, and libsrm's dependency (same soname)
+    # resolves to it instead of a second copy from /opt/rocm.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, dp = C.c_void_p, C.POINTER(C.c_double)
     L.srm_init.argtypes = [C.POINTER(Params), vp, vp, vp, C.c_double, C.c_int64, C.c_int32, vp,
@@ -91,9 +98,9 @@ def lib():
     L.srm_profile_enable.argtypes = [vp, C.c_int32]
     L.srm_profile_read.argtypes = [vp, C.POINTER(Profile)]
     L.srm_debug_fp.argtypes = [dp, dp, C.c_int64, dp, dp]
-    L.srm_debug_philox.argtypes = [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.c_int64,
-                                   C.POINTER(C.c_uint64)]
-    L.srm_debug_unitvec.argtypes = [C.c_int32, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64,
+    L.srm_debug_philox.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.c_int64,
+                                   C.POINTER(C.c_uint32)]
+    L.srm_debug_unitvec.argtypes = [C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                     C.c_double, C.c_int64, dp]
     for name in SYMBOLS:
         if name != "srm_last_error":
@@ -134,11 +141,11 @@ def debug_fp(a: np.ndarray, b: np.ndarray):
 
 
 def debug_philox(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
-    """Device Philox4x64-10 for ctr (n, 4) and key (n, 2) uint64."""
-    ctr = np.ascontiguousarray(ctr, dtype=np.uint64)
-    key = np.ascontiguousarray(key, dtype=np.uint64)
+    """Device Philox4x32-10 for ctr (n, 4) and key (n, 2) uint32."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32)
+    key = np.ascontiguousarray(key, dtype=np.uint32)
     out = np.empty_like(ctr)
-    up = C.POINTER(C.c_uint64)
+    up = C.POINTER(C.c_uint32)
     _check(lib().srm_debug_philox(ctr.ctypes.data_as(up), key.ctypes.data_as(up), ctr.shape[0],
                                   out.ctypes.data_as(up)))
     return out
@@ -147,8 +154,8 @@ def debug_philox(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
 def debug_unitvec(dim, seed, t, kind, k, l, stream, length, n) -> np.ndarray:
     """Device trial vectors for particle ids 0..n-1, shape (n, 3)."""
     out = np.empty((n, 3), dtype=np.float64)
-    kkl = (int(kind) << 48) | (int(k) << 32) | (int(l) << 16)
-    _check(lib().srm_debug_unitvec(int(dim), int(seed), int(t), kkl, int(stream), float(length),
+    word = (int(kind) << 31) | (int(k) << 16) | (int(l) << 8)
+    _check(lib().srm_debug_unitvec(int(dim), int(seed), int(t), word, int(stream), float(length),
                                    int(n), out.ctypes.data_as(C.POINTER(C.c_double))))
     return out
 

@@ -127,18 +127,12 @@ __device__ __forceinline__ bool is_interior(const Grid &g, int32_t cx, int32_t c
     return in;
 }
 
+// Algorithm 3 for the particles of one cell (global-memory path): slots
+// [beg, end) in ascending id order, each with up to N_l trials.
 template <int DIM, bool POLY>
-__global__ void __launch_bounds__(kBlock) k_migrate_ball(PassArgs a, ColourLattice L)
+__device__ __forceinline__ void migrate_cell_global(const PassArgs &a, int32_t cx, int32_t cy,
+                                                    int32_t cz)
 {
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= L.count) return;
-    const int32_t jx = t % L.h[0];
-    const int32_t r1 = t / L.h[0];
-    const int32_t jy = r1 % L.h[1];
-    const int32_t jz = r1 / L.h[1];
-    const int32_t cx = 2 * jx + L.off[0];
-    const int32_t cy = 2 * jy + L.off[1];
-    const int32_t cz = (DIM == 3) ? 2 * jz + L.off[2] : 0;
     const int32_t c = cx + a.g.na[0] * (cy + a.g.na[1] * cz);
     const int32_t beg = a.start[c], end = a.start[c + 1];
     if (beg == end) return;
@@ -150,12 +144,14 @@ __global__ void __launch_bounds__(kBlock) k_migrate_ball(PassArgs a, ColourLatti
     double *__restrict__ Z = a.buf.x[2];
     for (int32_t p = beg; p < end; ++p) {
         const double ox = X[p], oy = Y[p], oz = (DIM == 3) ? Z[p] : 0.0;
-        const uint64_t id = (uint64_t)a.buf.id[p];
+        const uint32_t id = (uint32_t)a.buf.id[p];
         const double Ri = POLY ? a.s * a.buf.rho[p] : a.s;
         uint8_t code = 0;
+        Draw d = a.draw;
         for (int32_t l = 1; l <= a.n_l; ++l) {
             double v[3];
-            unit_vector<DIM>(a.seed, id, a.t, a.kk | ((uint64_t)l << 16), 0, a.c_m, v);
+            d.word = a.draw.word | ((uint32_t)l << 8);
+            unit_vector<DIM>(d, id, 0, a.c_m, v);
             const double yx = wrap_coord(ox + v[0], a.g.box[0]);
             const double yy = wrap_coord(oy + v[1], a.g.box[1]);
             const double yz = (DIM == 3) ? wrap_coord(oz + v[2], a.g.box[2]) : 0.0;
@@ -170,6 +166,237 @@ __global__ void __launch_bounds__(kBlock) k_migrate_ball(PassArgs a, ColourLatti
             }
         }
         a.acc[p] = code;
+    }
+}
+
+// One thread per colour cell, candidates read from global memory (grids
+// too small for the tiled kernel).
+template <int DIM, bool POLY>
+__global__ void __launch_bounds__(kBlock) k_migrate_ball(PassArgs a, ColourLattice L)
+{
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= L.count) return;
+    const int32_t jx = t % L.h[0];
+    const int32_t r1 = t / L.h[0];
+    const int32_t jy = r1 % L.h[1];
+    const int32_t jz = r1 / L.h[1];
+    migrate_cell_global<DIM, POLY>(a, 2 * jx + L.off[0], 2 * jy + L.off[1],
+                                   (DIM == 3) ? 2 * jz + L.off[2] : 0);
+}
+
+// ------------------------------------------------------------ tiled kernel
+//
+// A 64-lane workgroup owns a tile of T^dim cells of the launch's colour
+// (T = 4 in 3D, 8 in 2D) and stages the (2T+1)^dim cells around them --
+// every cell any of its lanes can touch -- into LDS as SoA positions with a
+// local CSR index, copying whole cells per lane so that neighbouring lanes
+// read neighbouring addresses.  Each lane then runs Algorithm 3 for its own
+// cell against LDS, mirroring accepted moves to LDS (later particles of the
+// same cell see them) and to HBM.  No lane ever reads a cell another lane
+// writes (same colour), so LDS needs no synchronisation after staging.  A
+// tile whose neighbourhood exceeds the LDS capacity runs the global path.
+
+template <int DIM, bool POLY>
+struct TileCfg {
+    static constexpr int T = (DIM == 3) ? 4 : 8;
+    static constexpr int R = 2 * T + 1;
+    static constexpr int kCells = (DIM == 3) ? R * R * R : R * R;
+    static constexpr int kLanes = 64;
+    static constexpr int kPer = (kCells + kLanes - 1) / kLanes;  // region cells per lane
+    // LDS capacity in particles: ~40 KB per workgroup so four fit a CU.
+    static constexpr int kCap = (DIM == 3) ? (POLY ? 1152 : 1536) : (POLY ? 1536 : 2048);
+};
+
+__device__ __forceinline__ int32_t wave_inclusive_scan(int32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Candidate test against the LDS copy: the 3 (2D) or 9 (3D) rows of three
+// consecutive region cells around region cell (rx, ry, rz).
+template <int DIM, bool POLY, bool GENERAL>
+__device__ __forceinline__ bool lds_hits(const PassArgs &a, const double *sx, const double *sy,
+                                         const double *sz, const double *srho, const int32_t *lst,
+                                         int32_t rx, int32_t ry, int32_t rz, int32_t self,
+                                         double yx, double yy, double yz, double Ri)
+{
+    using C = TileCfg<DIM, POLY>;
+#pragma unroll
+    for (int iz = 0; iz < (DIM == 3 ? 3 : 1); ++iz) {
+#pragma unroll
+        for (int iy = 0; iy < 3; ++iy) {
+            const int32_t row = (ry + iy - 1) * C::R + ((DIM == 3) ? (rz + iz - 1) * C::R * C::R : 0);
+            const int32_t lo = lst[row + rx - 1], hi = lst[row + rx + 2];
+            for (int32_t q = lo; q < hi; ++q) {
+                if (q == self) continue;
+                double dx = yx - sx[q];
+                double dy = yy - sy[q];
+                if (GENERAL) {
+                    dx = min_image(dx, a.g.box[0], a.g.half[0]);
+                    dy = min_image(dy, a.g.box[1], a.g.half[1]);
+                }
+                double qq = dx * dx + dy * dy;
+                if (DIM == 3) {
+                    double dz = yz - sz[q];
+                    if (GENERAL) dz = min_image(dz, a.g.box[2], a.g.half[2]);
+                    qq = qq + dz * dz;
+                }
+                double sig2;
+                if (POLY) {
+                    const double sig = Ri + a.s * srho[q];
+                    sig2 = sig * sig;
+                } else {
+                    sig2 = a.sig2_mono;
+                }
+                if (qq <= sig2) return true;
+            }
+        }
+    }
+    return false;
+}
+
+struct TileLattice {
+    int32_t h[3];      // colour cells per axis
+    int32_t off[3];    // parity offset per axis
+    int32_t nt[3];     // tiles per axis
+    int32_t tiles;     // total tiles
+    int32_t per_xcd;   // tiles per XCD chunk (ceil(tiles / 8))
+};
+
+template <int DIM, bool POLY>
+__global__ void __launch_bounds__(64) k_migrate_tile(PassArgs a, TileLattice L)
+{
+    using C = TileCfg<DIM, POLY>;
+    __shared__ double sx[C::kCap];
+    __shared__ double sy[C::kCap];
+    __shared__ double sz[DIM == 3 ? C::kCap : 1];
+    __shared__ double srho[POLY ? C::kCap : 1];
+    __shared__ int32_t lst[C::kCells + 1];
+
+    // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous
+    // run of tiles so neighbouring tiles share its L2.
+    const int32_t b = blockIdx.x;
+    const int32_t tile = (b & 7) * L.per_xcd + (b >> 3);
+    if (tile >= L.tiles) return;
+    const int32_t tx = tile % L.nt[0];
+    const int32_t ty = (tile / L.nt[0]) % L.nt[1];
+    const int32_t tz = (DIM == 3) ? tile / (L.nt[0] * L.nt[1]) : 0;
+    const int lane = threadIdx.x;
+    const int32_t na0 = a.g.na[0], na1 = a.g.na[1], na2 = a.g.na[2];
+    // global cell of region cell 0 (one cell below the tile's first cell)
+    const int32_t ox = 2 * C::T * tx + L.off[0] - 1;
+    const int32_t oy = 2 * C::T * ty + L.off[1] - 1;
+    const int32_t oz = (DIM == 3) ? 2 * C::T * tz + L.off[2] - 1 : 0;
+
+    // 1. counts of the region cells and their global starts
+    int32_t gs[C::kPer];
+#pragma unroll
+    for (int j = 0; j < C::kPer; ++j) {
+        const int32_t r = lane + 64 * j;
+        gs[j] = 0;
+        if (r < C::kCells) {
+            const int32_t rx = r % C::R, ry = (r / C::R) % C::R;
+            const int32_t rz = (DIM == 3) ? r / (C::R * C::R) : 0;
+            const int32_t gx = wrap_index(ox + rx, na0), gy = wrap_index(oy + ry, na1);
+            const int32_t gz = (DIM == 3) ? wrap_index(oz + rz, na2) : 0;
+            const int32_t gc = gx + na0 * (gy + na1 * gz);
+            const int32_t g0 = a.start[gc];
+            gs[j] = g0;
+            lst[r] = a.start[gc + 1] - g0;
+        }
+    }
+    __syncthreads();
+    // 2. exclusive scan -> local CSR starts
+    int32_t carry = 0;
+    for (int base = 0; base < C::kCells; base += 64) {
+        const int32_t r = base + lane;
+        const int32_t v = (r < C::kCells) ? lst[r] : 0;
+        const int32_t inc = wave_inclusive_scan(v);
+        if (r < C::kCells) lst[r] = carry + inc - v;
+        carry += __shfl(inc, 63, 64);
+    }
+    if (lane == 0) lst[C::kCells] = carry;
+    __syncthreads();
+
+    // own colour cell of this lane
+    const int32_t lx = lane % C::T;
+    const int32_t ly = (lane / C::T) % C::T;
+    const int32_t lz = (DIM == 3) ? lane / (C::T * C::T) : 0;
+    const int32_t jx = C::T * tx + lx, jy = C::T * ty + ly, jz = (DIM == 3) ? C::T * tz + lz : 0;
+    const bool active = jx < L.h[0] && jy < L.h[1] && (DIM == 2 || jz < L.h[2]) &&
+                        (DIM == 3 || lane < C::T * C::T);
+    const int32_t cx = 2 * jx + L.off[0], cy = 2 * jy + L.off[1];
+    const int32_t cz = (DIM == 3) ? 2 * jz + L.off[2] : 0;
+
+    if (carry > C::kCap) {
+        // 3'. over capacity: global-memory path for this tile
+        if (active) migrate_cell_global<DIM, POLY>(a, cx, cy, cz);
+        return;
+    }
+    // 3. stage positions: lane copies whole cells
+#pragma unroll
+    for (int j = 0; j < C::kPer; ++j) {
+        const int32_t r = lane + 64 * j;
+        if (r < C::kCells) {
+            const int32_t d0 = lst[r], n = lst[r + 1] - d0, g0 = gs[j];
+            for (int32_t k = 0; k < n; ++k) {
+                sx[d0 + k] = a.buf.x[0][g0 + k];
+                sy[d0 + k] = a.buf.x[1][g0 + k];
+                if (DIM == 3) sz[d0 + k] = a.buf.x[2][g0 + k];
+                if (POLY) srho[d0 + k] = a.buf.rho[g0 + k];
+            }
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+
+    // 4. Algorithm 3 for the lane's cell against the LDS copy
+    const int32_t rx = 2 * lx + 1, ry = 2 * ly + 1, rz = (DIM == 3) ? 2 * lz + 1 : 0;
+    const int32_t ro = rx + C::R * (ry + C::R * rz);
+    const int32_t lb = lst[ro], le = lst[ro + 1];
+    if (lb == le) return;
+    const int32_t gb = a.start[cx + na0 * (cy + na1 * cz)];
+    const bool general = !is_interior<DIM>(a.g, cx, cy, cz);
+    double *__restrict__ X = a.buf.x[0];
+    double *__restrict__ Y = a.buf.x[1];
+    double *__restrict__ Z = a.buf.x[2];
+    for (int32_t p = lb; p < le; ++p) {
+        const int32_t gp = gb + (p - lb);
+        const double px = sx[p], py = sy[p], pz = (DIM == 3) ? sz[p] : 0.0;
+        const uint32_t id = (uint32_t)a.buf.id[gp];
+        const double Ri = POLY ? a.s * srho[p] : a.s;
+        uint8_t code = 0;
+        Draw d = a.draw;
+        for (int32_t l = 1; l <= a.n_l; ++l) {
+            double v[3];
+            d.word = a.draw.word | ((uint32_t)l << 8);
+            unit_vector<DIM>(d, id, 0, a.c_m, v);
+            const double yx = wrap_coord(px + v[0], a.g.box[0]);
+            const double yy = wrap_coord(py + v[1], a.g.box[1]);
+            const double yz = (DIM == 3) ? wrap_coord(pz + v[2], a.g.box[2]) : 0.0;
+            const bool hit =
+                general ? lds_hits<DIM, POLY, true>(a, sx, sy, sz, srho, lst, rx, ry, rz, p, yx, yy,
+                                                    yz, Ri)
+                        : lds_hits<DIM, POLY, false>(a, sx, sy, sz, srho, lst, rx, ry, rz, p, yx,
+                                                     yy, yz, Ri);
+            if (!hit) {
+                sx[p] = yx;
+                sy[p] = yy;
+                if (DIM == 3) sz[p] = yz;
+                X[gp] = yx;
+                Y[gp] = yy;
+                if (DIM == 3) Z[gp] = yz;
+                code = (uint8_t)l;
+                break;
+            }
+        }
+        a.acc[gp] = code;
     }
 }
 
@@ -264,14 +491,15 @@ __global__ void __launch_bounds__(kBlock) k_migrate_platelet(PassArgs a, ColourL
         const int32_t pid = a.buf.id[p];
         const double ai = a.buf.rho ? a.s * a.buf.rho[p] : a.s;
         uint8_t code = 0;
+        Draw d = a.draw;
         for (int32_t l = 1; l <= a.n_l; ++l) {
-            const uint64_t kkl = a.kk | ((uint64_t)l << 16);
+            d.word = a.draw.word | ((uint32_t)l << 8);
             double v[3], w[3];
-            unit_vector<3>(a.seed, (uint64_t)pid, a.t, kkl, 0, a.c_m, v);
+            unit_vector<3>(d, (uint32_t)pid, 0, a.c_m, v);
             const double yx = wrap_coord(ox + v[0], a.g.box[0]);
             const double yy = wrap_coord(oy + v[1], a.g.box[1]);
             const double yz = wrap_coord(oz + v[2], a.g.box[2]);
-            unit_vector<3>(a.seed, (uint64_t)pid, a.t, kkl, 1, a.c_n, w);
+            unit_vector<3>(d, (uint32_t)pid, 1, a.c_n, w);
             const double m0 = n0 + w[0], m1 = n1 + w[1], m2 = n2 + w[2];
             const double mm = m0 * m0 + m1 * m1 + m2 * m2;
             const double inv = 1.0 / __builtin_sqrt(mm);
@@ -335,6 +563,16 @@ bool colour_lattice(int dim, const Grid &g, int colour, ColourLattice &L)
     return L.count > 0;
 }
 
+// The tiled kernel needs at least 2T+1 distinct cells on every axis so that
+// a region never holds a cell twice.
+bool tile_ok(int dim, const Grid &g)
+{
+    const int need = (dim == 3) ? 9 : 17;
+    for (int ax = 0; ax < dim; ++ax)
+        if (g.na[ax] < need) return false;
+    return true;
+}
+
 }  // namespace
 
 hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int colour,
@@ -343,6 +581,28 @@ hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int 
     ColourLattice L;
     *launched = false;
     if (!colour_lattice(dim, a.g, colour, L)) return hipSuccess;
+    if (shape != SRM_PLATELET && tile_ok(dim, a.g)) {
+        TileLattice T{};
+        const int tsz = (dim == 3) ? 4 : 8;
+        T.tiles = 1;
+        for (int ax = 0; ax < 3; ++ax) {
+            T.h[ax] = L.h[ax];
+            T.off[ax] = L.off[ax];
+            T.nt[ax] = (ax < dim) ? (L.h[ax] + tsz - 1) / tsz : 1;
+            T.tiles *= T.nt[ax];
+        }
+        T.per_xcd = (T.tiles + 7) / 8;
+        const dim3 grid(8 * T.per_xcd), block(64);
+        if (dim == 3) {
+            if (poly) hipLaunchKernelGGL((k_migrate_tile<3, true>), grid, block, 0, stream, a, T);
+            else hipLaunchKernelGGL((k_migrate_tile<3, false>), grid, block, 0, stream, a, T);
+        } else {
+            if (poly) hipLaunchKernelGGL((k_migrate_tile<2, true>), grid, block, 0, stream, a, T);
+            else hipLaunchKernelGGL((k_migrate_tile<2, false>), grid, block, 0, stream, a, T);
+        }
+        *launched = true;
+        return hipGetLastError();
+    }
     const dim3 grid(blocks_for(L.count)), block(kBlock);
     if (shape == SRM_PLATELET) {
         hipLaunchKernelGGL(k_migrate_platelet, grid, block, 0, stream, a, L);

@@ -239,9 +239,10 @@ PassArgs pass_args(srm_ctx *c, const PBuf &b, const Grid &g, double s, int kind,
     a.s = s;
     const double sig = s + s;
     a.sig2_mono = sig * sig;
-    a.seed = c->p.seed;
-    a.t = (uint64_t)c->t;
-    a.kk = ((uint64_t)(uint32_t)kind << 48) | ((uint64_t)(uint32_t)k << 32);
+    a.draw.key0 = (uint32_t)c->p.seed;
+    a.draw.key1 = (uint32_t)(c->p.seed >> 32);
+    a.draw.t = (uint32_t)c->t;
+    a.draw.word = counter_word((uint32_t)kind, (uint32_t)k, 0);
     a.n_l = c->p.n_l;
     a.c_m = c->p.c_m;
     a.c_n = c->p.c_n;
@@ -296,7 +297,7 @@ srm_status check_params(const srm_params *p)
     if (!(p->c_w >= 0.0) || !(p->c_m >= 0.0) || !(p->c_n >= 0.0) || !isfinite(p->c_m) ||
         !isfinite(p->c_w) || !isfinite(p->c_n))
         return fail(SRM_EINVAL, "rates must be finite and >= 0");
-    if (p->n_k < 0 || p->n_k > 65535) return fail(SRM_EINVAL, "n_k out of range");
+    if (p->n_k < 0 || p->n_k > 32767) return fail(SRM_EINVAL, "n_k out of range");
     if (p->n_l < 0 || p->n_l > 255) return fail(SRM_EINVAL, "n_l out of range");
     return SRM_OK;
 }
@@ -318,7 +319,7 @@ srm_status srm_init(const srm_params *p, const double *pos, const double *rho,
         return fail(SRM_EINVAL, "bad mem_kind");
     if (p->shape == SRM_PLATELET && !normals) return fail(SRM_EINVAL, "platelets need normals");
     if (!(s0 >= 0.0) || !isfinite(s0)) return fail(SRM_EINVAL, "bad s0");
-    if (sweep0 < 0) return fail(SRM_EINVAL, "sweep0 < 0");
+    if (sweep0 < 0 || sweep0 > 0xffffffffLL) return fail(SRM_EINVAL, "sweep0 out of range");
 
     srm_ctx *c = new (std::nothrow) srm_ctx();
     if (!c) return fail(SRM_ENOMEM, "host allocation failed");
@@ -425,6 +426,7 @@ srm_status srm_free(srm_ctx *c)
 srm_status srm_sweep(srm_ctx *c, srm_sweep_info *info)
 {
     if (!c) return fail(SRM_EINVAL, "ctx is NULL");
+    if (c->t >= 0xffffffffLL) return fail(SRM_EINVAL, "sweep counter exhausted (2^32 - 1)");
     const double s1 = swell(c, c->s);
     const Grid g = make_grid(c, s1 * c->rho_max);
     srm_status st;
@@ -555,7 +557,7 @@ srm_status srm_pass(srm_ctx *c, double grid_s, double radius_s, int32_t kind, in
 {
     if (!c) return fail(SRM_EINVAL, "ctx is NULL");
     if (kind != SRM_PASS_MAIN && kind != SRM_PASS_SHAKE) return fail(SRM_EINVAL, "bad kind");
-    if (k < 0 || k > 65535) return fail(SRM_EINVAL, "k out of range");
+    if (k < 0 || k > 32767) return fail(SRM_EINVAL, "k out of range");
     const Grid g = make_grid(c, grid_s * c->rho_max);
     srm_status st;
     if ((st = bin(c, c->P, c->T, g))) return st;
@@ -644,32 +646,32 @@ srm_status srm_debug_fp(const double *a, const double *b, int64_t n, double *sqr
     return SRM_OK;
 }
 
-srm_status srm_debug_philox(const uint64_t *ctr, const uint64_t *key, int64_t n, uint64_t *out)
+srm_status srm_debug_philox(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32_t *out)
 {
     if (n < 0 || n > 0x0fffffffLL || (n > 0 && (!ctr || !key || !out)))
         return fail(SRM_EINVAL, "bad arguments");
     if (n == 0) return SRM_OK;
     DevArena d;
-    HIP_TRY(hipMalloc(&d.p[0], (size_t)n * 32));
-    HIP_TRY(hipMalloc(&d.p[1], (size_t)n * 16));
-    HIP_TRY(hipMalloc(&d.p[2], (size_t)n * 32));
-    HIP_TRY(hipMemcpy(d.p[0], ctr, (size_t)n * 32, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d.p[1], key, (size_t)n * 16, hipMemcpyHostToDevice));
-    HIP_TRY(diag_philox((const uint64_t *)d.p[0], (const uint64_t *)d.p[1], (int32_t)n,
-                        (uint64_t *)d.p[2], nullptr));
-    HIP_TRY(hipMemcpy(out, d.p[2], (size_t)n * 32, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMalloc(&d.p[0], (size_t)n * 16));
+    HIP_TRY(hipMalloc(&d.p[1], (size_t)n * 8));
+    HIP_TRY(hipMalloc(&d.p[2], (size_t)n * 16));
+    HIP_TRY(hipMemcpy(d.p[0], ctr, (size_t)n * 16, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.p[1], key, (size_t)n * 8, hipMemcpyHostToDevice));
+    HIP_TRY(diag_philox((const uint32_t *)d.p[0], (const uint32_t *)d.p[1], (int32_t)n,
+                        (uint32_t *)d.p[2], nullptr));
+    HIP_TRY(hipMemcpy(out, d.p[2], (size_t)n * 16, hipMemcpyDeviceToHost));
     return SRM_OK;
 }
 
-srm_status srm_debug_unitvec(int32_t dim, uint64_t seed, uint64_t t, uint64_t kkl,
-                             uint64_t stream, double len, int64_t n, double *out)
+srm_status srm_debug_unitvec(int32_t dim, uint64_t seed, uint32_t t, uint32_t word,
+                             uint32_t stream, double len, int64_t n, double *out)
 {
     if ((dim != 2 && dim != 3) || n < 0 || n > 0x0fffffffLL || (n > 0 && !out))
         return fail(SRM_EINVAL, "bad arguments");
     if (n == 0) return SRM_OK;
     DevArena d;
     HIP_TRY(hipMalloc(&d.p[0], (size_t)n * 24));
-    HIP_TRY(diag_unitvec(dim, seed, t, kkl, stream, len, (int32_t)n, (double *)d.p[0], nullptr));
+    HIP_TRY(diag_unitvec(dim, seed, t, word, stream, len, (int32_t)n, (double *)d.p[0], nullptr));
     HIP_TRY(hipMemcpy(out, d.p[0], (size_t)n * 24, hipMemcpyDeviceToHost));
     return SRM_OK;
 }

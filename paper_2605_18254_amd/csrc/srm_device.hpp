@@ -26,20 +26,21 @@ struct Grid {
 };
 
 // ---------------------------------------------------------------------------
-// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the
-// 4-word multiply/xor bijection with a Weyl-sequence key schedule.
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the
+// 4-word multiply/xor bijection with a Weyl-sequence key schedule.  The key
+// schedule is the same for every lane, so it stays in scalar registers.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void philox4x64_10(uint64_t &x0, uint64_t &x1, uint64_t &x2,
-                                              uint64_t &x3, uint64_t k0, uint64_t k1)
+__device__ __forceinline__ void philox4x32_10(uint32_t &x0, uint32_t &x1, uint32_t &x2,
+                                              uint32_t &x3, uint32_t k0, uint32_t k1)
 {
-    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint64_t lo0 = M0 * x0, hi0 = __umul64hi(M0, x0);
-        const uint64_t lo1 = M1 * x2, hi1 = __umul64hi(M1, x2);
-        const uint64_t y0 = hi1 ^ x1 ^ k0;
-        const uint64_t y2 = hi0 ^ x3 ^ k1;
+        const uint32_t lo0 = M0 * x0, hi0 = __umulhi(M0, x0);
+        const uint32_t lo1 = M1 * x2, hi1 = __umulhi(M1, x2);
+        const uint32_t y0 = hi1 ^ x1 ^ k0;
+        const uint32_t y2 = hi0 ^ x3 ^ k1;
         x0 = y0;
         x1 = lo1;
         x2 = y2;
@@ -49,29 +50,50 @@ __device__ __forceinline__ void philox4x64_10(uint64_t &x0, uint64_t &x1, uint64
     }
 }
 
-// Random vector of length `len` with uniform direction: Philox words
-// mapped to w_a = 2 u_a - 1 (u_a = (W_a >> 11) 2^-53, exact), rejected
-// unless 0 < |w|^2 <= 1, then scaled by len / sqrt(|w|^2).  Counter
-// (id, t, kind<<48 | k<<32 | l<<16 | round, stream), key (seed, 0).
+// Odd multiple of 2^-32 in (-1, 1) from a 32-bit word (all steps exact).
+__device__ __forceinline__ double sym_uniform(uint32_t w)
+{
+    return ((double)w - 2147483647.5) * 0x1p-31;
+}
+
+// Counter-based draw parameters of one particle's trial moves.
+struct Draw {
+    uint32_t key0, key1;  // seed
+    uint32_t t;           // sweep counter
+    uint32_t word;        // kind<<31 | k<<16 | l<<8
+};
+
+// Random vector of length `len` with uniform direction.  Each Philox call
+// (counter (id, t, word | call, stream)) gives two attempts (v1, v2) in
+// (-1,1)^2, kept when s = v1^2 + v2^2 < 1.  3D: Marsaglia's point on the
+// sphere (2 v1 sqrt(1-s), 2 v2 sqrt(1-s), 1 - 2s) times len; 2D:
+// (v1, v2) * (len / sqrt(s)).
 template <int DIM>
-__device__ __forceinline__ void unit_vector(uint64_t seed, uint64_t id, uint64_t t,
-                                            uint64_t kkl, uint64_t stream, double len,
-                                            double v[3])
+__device__ __forceinline__ void unit_vector(const Draw &d, uint32_t id, uint32_t stream,
+                                            double len, double v[3])
 {
     for (uint32_t r = 0; r < 64; ++r) {
-        uint64_t x0 = id, x1 = t, x2 = kkl | (uint64_t)r, x3 = stream;
-        philox4x64_10(x0, x1, x2, x3, seed, 0);
-        const double w0 = 2.0 * ((double)(x0 >> 11) * 0x1p-53) - 1.0;
-        const double w1 = 2.0 * ((double)(x1 >> 11) * 0x1p-53) - 1.0;
-        const double w2 = 2.0 * ((double)(x2 >> 11) * 0x1p-53) - 1.0;
-        double q = w0 * w0 + w1 * w1;
-        if (DIM == 3) q = q + w2 * w2;
-        if (q > 0.0 && q <= 1.0) {
-            const double g = len / __builtin_sqrt(q);
-            v[0] = w0 * g;
-            v[1] = w1 * g;
-            v[2] = (DIM == 3) ? w2 * g : 0.0;
-            return;
+        uint32_t w[4] = {id, d.t, d.word | r, stream};
+        philox4x32_10(w[0], w[1], w[2], w[3], d.key0, d.key1);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const double v1 = sym_uniform(w[2 * a]);
+            const double v2 = sym_uniform(w[2 * a + 1]);
+            const double s = v1 * v1 + v2 * v2;
+            if (s < 1.0) {
+                if (DIM == 3) {
+                    const double h = 2.0 * __builtin_sqrt(1.0 - s);
+                    v[0] = (v1 * h) * len;
+                    v[1] = (v2 * h) * len;
+                    v[2] = (1.0 - 2.0 * s) * len;
+                } else {
+                    const double g = len / __builtin_sqrt(s);
+                    v[0] = v1 * g;
+                    v[1] = v2 * g;
+                    v[2] = 0.0;
+                }
+                return;
+            }
         }
     }
     v[0] = len;
@@ -79,9 +101,9 @@ __device__ __forceinline__ void unit_vector(uint64_t seed, uint64_t id, uint64_t
     v[2] = 0.0;
 }
 
-__device__ __forceinline__ uint64_t counter_word(uint32_t kind, uint32_t k, uint32_t l)
+__host__ __device__ __forceinline__ uint32_t counter_word(uint32_t kind, uint32_t k, uint32_t l)
 {
-    return ((uint64_t)kind << 48) | ((uint64_t)k << 32) | ((uint64_t)l << 16);
+    return (kind << 31) | (k << 16) | (l << 8);
 }
 
 // Algorithm 4: if x < 0 add L, then if x >= L subtract L.

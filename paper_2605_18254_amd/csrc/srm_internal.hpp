@@ -71,9 +71,7 @@ struct PassArgs {
     int32_t n;
     double s;          // radius scale of this pass
     double sig2_mono;  // (s + s)^2 for monodisperse balls
-    uint64_t seed;
-    uint64_t t;
-    uint64_t kk;       // kind<<48 | k<<32
+    Draw draw;         // key, sweep, kind<<31 | k<<16 (trial l added per draw)
     int32_t n_l;
     double c_m, c_n;
 };
@@ -90,9 +88,9 @@ hipError_t check_overlaps(int dim, int shape, bool poly, const PassArgs &a, bool
 // Diagnostics of the device arithmetic (k_diag.hip).
 hipError_t diag_fp(const double *a, const double *b, int32_t n, double *sq, double *dv,
                    hipStream_t s);
-hipError_t diag_philox(const uint64_t *ctr, const uint64_t *key, int32_t n, uint64_t *out,
+hipError_t diag_philox(const uint32_t *ctr, const uint32_t *key, int32_t n, uint32_t *out,
                        hipStream_t s);
-hipError_t diag_unitvec(int dim, uint64_t seed, uint64_t t, uint64_t kkl, uint64_t stream,
+hipError_t diag_unitvec(int dim, uint64_t seed, uint32_t t, uint32_t word, uint32_t stream,
                         double len, int32_t n, double *out, hipStream_t s);
 
 }  // namespace srm

@@ -61,8 +61,9 @@ def test_device_sqrt_and_division_correctly_rounded(srm):
     b = np.concatenate([rng.random(n // 2) + 1e-3, np.exp(rng.uniform(-300, 300, n // 2)),
                         [1.0, 3.0, 7.0, 0.1, 3.0, 2.0, 0.5]])
     sq, dv = srm.debug_fp(a, b)
-    assert np.array_equal(sq, np.sqrt(a))
-    assert np.array_equal(dv, a / b)
+    with np.errstate(over="ignore", under="ignore"):
+        assert np.array_equal(sq, np.sqrt(a))
+        assert np.array_equal(dv, a / b)
     # the values the unit-vector draw actually sees: q in (0, 1]
     q = rng.random(n) + 2.0**-53
     sq, dv = srm.debug_fp(q, np.sqrt(q))
@@ -70,19 +71,13 @@ def test_device_sqrt_and_division_correctly_rounded(srm):
     assert np.array_equal(dv, q / np.sqrt(q))
 
 
-def test_device_philox_matches_numpy(srm):
+def test_device_philox_matches_rocrand(srm):
+    from tests import rocrand_ref
     rng = np.random.default_rng(1)
-    n = 20000
-    ctr = rng.integers(0, 2**63, size=(n, 4), dtype=np.int64).astype(np.uint64) * np.uint64(2)
-    ctr += rng.integers(0, 2, size=(n, 4)).astype(np.uint64)
-    key = rng.integers(0, 2**63, size=(n, 2), dtype=np.int64).astype(np.uint64)
-    out = srm.debug_philox(ctr, key)
-    for i in range(0, n, 97):
-        c = [int(x) for x in ctr[i]]
-        cint = c[0] | (c[1] << 64) | (c[2] << 128) | (c[3] << 192)
-        bg = np.random.Philox(key=int(key[i, 0]) | (int(key[i, 1]) << 64),
-                              counter=(cint - 1) % (1 << 256))
-        assert np.array_equal(bg.random_raw(4), out[i])
+    n = 200000
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2**32, size=(n, 2), dtype=np.uint64).astype(np.uint32)
+    assert np.array_equal(srm.debug_philox(ctr, key), rocrand_ref.philox4x32(ctr, key))
 
 
 @pytest.mark.parametrize("dim,stream", [(2, 0), (3, 0), (3, 1)])
@@ -160,7 +155,7 @@ def test_config1_full_run_bitexact(srm, oracle_lib):
     w = srm_inputs.make("disks2d")
     o, g, sweeps = _sweep_parity(srm, oracle_lib, w, 1000)
     assert o.s == w.s_target
-    _say(f"config 1: {sweeps} sweeps, fraction {g.sweep()['fraction'] if False else o.fraction()}")
+    _say(f"config 1: {sweeps} sweeps, fraction {o.fraction()}")
     g.close()
 
 

@@ -1,8 +1,8 @@
 """Pins of the CPU oracle against facts fixed outside it.
 
-* Philox4x64-10 against numpy's independent implementation (bitwise).
-* Unit vectors: exact norm, isotropy, and the direction drawn from numpy's
-  Philox words at the first accepted rejection round.
+* Philox4x32-10 against rocRAND's independent implementation (bitwise).
+* Unit vectors: norm, isotropy, acceptance rate, and the direction computed
+  in long double from rocRAND's words at the first accepted attempt.
 * Cell size and binning against their definitions and the completeness
   requirement (every overlapping pair lies in neighbouring cells).
 * A migration pass replayed particle by particle with all-pairs brute-force
@@ -19,34 +19,39 @@ import numpy as np
 import pytest
 
 import srm_inputs
-from tests import brute
-
-MASK64 = (1 << 64) - 1
+from tests import brute, rocrand_ref
 
 
-def test_philox_matches_numpy(oracle_lib):
+
+def test_philox4x32_matches_rocrand(oracle_lib):
     rng = np.random.default_rng(7)
-    for _ in range(200):
-        ctr = [int(x) for x in rng.integers(0, 2**63, 4, dtype=np.int64)]
-        ctr = [(c << 1) | int(rng.integers(0, 2)) for c in ctr]
-        key = [int(x) for x in rng.integers(0, 2**63, 2, dtype=np.int64)]
-        cint = ctr[0] | (ctr[1] << 64) | (ctr[2] << 128) | (ctr[3] << 192)
-        bg = np.random.Philox(key=key[0] | (key[1] << 64), counter=(cint - 1) % (1 << 256))
-        ref = bg.random_raw(4)
-        got = oracle_lib.philox(ctr, key)
-        assert np.array_equal(ref, got), (ctr, key)
+    n = 300
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2**32, size=(n, 2), dtype=np.uint64).astype(np.uint32)
+    ctr[0], key[0] = 0, 0
+    ctr[1], key[1] = 0xFFFFFFFF, 0xFFFFFFFF
+    ref = rocrand_ref.philox4x32(ctr, key)
+    for i in range(n):
+        assert np.array_equal(oracle_lib.philox4x32(ctr[i], key[i]), ref[i]), i
 
 
-def _numpy_direction(dim, seed, pid, t, kind, k, l, stream):
-    """First rejection round with 0 < |w|^2 <= 1, w from numpy Philox words."""
+def _ref_direction(dim, seed, pid, t, kind, k, l, stream):
+    """First accepted attempt from rocRAND words, in long double: the unit
+    vector (2 v1 sqrt(1-s), 2 v2 sqrt(1-s), 1-2s) or (v1, v2)/sqrt(s)."""
     for r in range(64):
-        c2 = (kind << 48) | (k << 32) | (l << 16) | r
-        cint = pid | (t << 64) | (c2 << 128) | (stream << 192)
-        W = np.random.Philox(key=seed, counter=cint - 1).random_raw(4)
-        w = 2.0 * ((W[:dim] >> np.uint64(11)).astype(np.float64) * 2.0**-53) - 1.0
-        q = float(np.sum(w.astype(np.longdouble) ** 2))
-        if 0.0 < q <= 1.0:
-            return w / math.sqrt(q), r + 1
+        ctr = np.array([[pid, t, (kind << 31) | (k << 16) | (l << 8) | r, stream]],
+                       dtype=np.uint64).astype(np.uint32)
+        key = np.array([[seed & 0xFFFFFFFF, seed >> 32]], dtype=np.uint64).astype(np.uint32)
+        W = rocrand_ref.philox4x32(ctr, key)[0].astype(np.longdouble)
+        for a in range(2):
+            v1 = (W[2 * a] - np.longdouble(2147483647.5)) / np.longdouble(2**31)
+            v2 = (W[2 * a + 1] - np.longdouble(2147483647.5)) / np.longdouble(2**31)
+            s = v1 * v1 + v2 * v2
+            if s < 1:
+                if dim == 3:
+                    h = 2 * np.sqrt(1 - s)
+                    return np.array([v1 * h, v2 * h, 1 - 2 * s]), r + 1
+                return np.array([v1, v2]) / np.sqrt(s), r + 1
     return None, 65
 
 
@@ -55,11 +60,11 @@ def test_unitvec_direction_and_norm(oracle_lib, dim):
     c_m = 3.7e-4
     for pid in range(300):
         v, rounds = oracle_lib.unitvec(dim, 11, pid, 5, 0, 2, 3, 0, c_m)
-        u, r_ref = _numpy_direction(dim, 11, pid, 5, 0, 2, 3, 0)
+        u, r_ref = _ref_direction(dim, 11, pid, 5, 0, 2, 3, 0)
         assert rounds == r_ref
         norm = math.sqrt(float(np.sum(v[:dim].astype(np.longdouble) ** 2)))
         assert abs(norm / c_m - 1.0) < 4e-16 * 4
-        assert np.allclose(v[:dim] / c_m, u, rtol=0, atol=4e-16 * 4)
+        assert np.allclose(v[:dim] / c_m, u.astype(np.float64), rtol=0, atol=4e-16 * 4)
         if dim == 2:
             assert v[2] == 0.0
 
@@ -74,9 +79,10 @@ def test_unitvec_isotropic(oracle_lib, dim):
     assert np.allclose(np.diag(cov), 1.0 / dim, atol=5 * math.sqrt(2.0 / n) / dim)
     off = cov[~np.eye(dim, dtype=bool)]
     assert np.all(np.abs(off) < 5 * math.sqrt(1.0 / n) / dim)
-    # acceptance of the rejection sampler: pi/4 (2D) or pi/6 (3D) per round
+    # acceptance: two attempts per Philox call, each kept with probability
+    # pi/4, so a call succeeds with p = 1 - (1 - pi/4)^2
     rounds = np.array([oracle_lib.unitvec(dim, 3, i, 0, 1, 1, 1, 0, 1.0)[1] for i in range(n)])
-    p = math.pi / 4 if dim == 2 else math.pi / 6
+    p = 1.0 - (1.0 - math.pi / 4) ** 2
     assert abs(rounds.mean() - 1.0 / p) < 5 * math.sqrt((1 - p) / p**2 / n)
 
 
@@ -273,7 +279,8 @@ def test_single_particle_moves_by_first_trial(oracle_lib):
         pos = np.full((dim, 1), 0.999) if dim == 2 else np.array([[0.0005], [0.5], [0.999]])
         o = oracle_lib.Oracle(dim=dim, n=1, s_target=0.1, c_w=0.01, c_m=0.003, n_k=8, n_l=8,
                               seed=77, pos=pos, sweep0=9)
-        u, _ = _numpy_direction(dim, 77, 0, 9, 0, 1, 1, 0)
+        u, _ = _ref_direction(dim, 77, 0, 9, 0, 1, 1, 0)
+        u = u.astype(np.float64)
         info, acc = o.sweep()
         assert info["committed"] and info["passes_main"] == 1 and acc[0] == 1
         for a in range(dim):
