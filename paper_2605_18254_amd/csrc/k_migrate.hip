@@ -186,25 +186,46 @@ __global__ void __launch_bounds__(kBlock) k_migrate_ball(PassArgs a, ColourLatti
 
 // ------------------------------------------------------------ tiled kernel
 //
-// A 64-lane workgroup owns a tile of T^dim cells of the launch's colour
-// (T = 4 in 3D, 8 in 2D) and stages the (2T+1)^dim cells around them --
-// every cell any of its lanes can touch -- into LDS as SoA positions with a
-// local CSR index, copying whole cells per lane so that neighbouring lanes
-// read neighbouring addresses.  Each lane then runs Algorithm 3 for its own
-// cell against LDS, mirroring accepted moves to LDS (later particles of the
-// same cell see them) and to HBM.  No lane ever reads a cell another lane
-// writes (same colour), so LDS needs no synchronisation after staging.  A
-// tile whose neighbourhood exceeds the LDS capacity runs the global path.
+// A 256-thread workgroup owns a tile of 64 cells of the launch's colour
+// (4x4x4 in 3D, 8x8 in 2D) and stages the (2T+1)^dim cells around them --
+// every cell its lanes can touch -- into LDS as SoA positions with a local
+// CSR index; each thread copies whole cells so neighbouring threads read
+// neighbouring addresses.  Four lanes (a quad) serve one cell and process
+// its particles in ascending id order:
+//  * the quad scans the 3^dim stencil once per particle and keeps the
+//    candidates whose distance to the particle's old position is at most
+//    R_i + R_j + 2 c_m (a superset of every particle a trial position within
+//    c_m of it can touch; the exact test below decides);
+//  * lane j of the quad draws trial l = base + j and tests it exactly
+//    against that short list; the lowest collision-free trial of the batch
+//    is accepted -- the first free trial of the sequential rule, since all
+//    trials of one particle are tested against the same neighbour state.
+// Accepted moves go to LDS (later particles of the cell see them) and HBM.
+// No quad reads a cell another quad writes (same colour), so LDS needs no
+// synchronisation after staging.  A tile whose neighbourhood does not fit
+// LDS is queued for the global-memory kernel.
 
 template <int DIM, bool POLY>
-struct TileCfg {
+struct QuadCfg {
     static constexpr int T = (DIM == 3) ? 4 : 8;
     static constexpr int R = 2 * T + 1;
     static constexpr int kCells = (DIM == 3) ? R * R * R : R * R;
-    static constexpr int kLanes = 64;
-    static constexpr int kPer = (kCells + kLanes - 1) / kLanes;  // region cells per lane
+    static constexpr int kThreads = 256;
+    static constexpr int kPer = (kCells + kThreads - 1) / kThreads;
+    static constexpr int kNear = 16;
     // LDS capacity in particles: ~40 KB per workgroup so four fit a CU.
-    static constexpr int kCap = (DIM == 3) ? (POLY ? 1152 : 1536) : (POLY ? 1536 : 2048);
+    static constexpr int kCap = (DIM == 3) ? (POLY ? 1088 : 1472) : (POLY ? 1536 : 2176);
+};
+
+struct TileLattice {
+    int32_t h[3];      // colour cells per axis
+    int32_t off[3];    // parity offset per axis
+    int32_t nt[3];     // tiles per axis
+    int32_t tiles;     // total tiles
+    int32_t per_xcd;   // tiles per XCD chunk (ceil(tiles / 8))
+    int32_t colour;
+    int32_t *ovf;      // [8] counts, then 8 lists of max_tiles tile ids
+    int32_t max_tiles;
 };
 
 __device__ __forceinline__ int32_t wave_inclusive_scan(int32_t v)
@@ -218,6 +239,22 @@ __device__ __forceinline__ int32_t wave_inclusive_scan(int32_t v)
     return v;
 }
 
+// Bits of the calling lane's quad in a wave-wide ballot.
+__device__ __forceinline__ uint32_t quad_bits(unsigned long long m)
+{
+    const int sh = (threadIdx.x & 63) & ~3;
+    return (uint32_t)(m >> sh) & 0xFu;
+}
+
+template <int DIM>
+__device__ __forceinline__ void tile_coords(const TileLattice &L, int32_t tile, int32_t &tx,
+                                            int32_t &ty, int32_t &tz)
+{
+    tx = tile % L.nt[0];
+    ty = (tile / L.nt[0]) % L.nt[1];
+    tz = (DIM == 3) ? tile / (L.nt[0] * L.nt[1]) : 0;
+}
+
 // Candidate test against the LDS copy: the 3 (2D) or 9 (3D) rows of three
 // consecutive region cells around region cell (rx, ry, rz).
 template <int DIM, bool POLY, bool GENERAL>
@@ -226,7 +263,7 @@ __device__ __forceinline__ bool lds_hits(const PassArgs &a, const double *sx, co
                                          int32_t rx, int32_t ry, int32_t rz, int32_t self,
                                          double yx, double yy, double yz, double Ri)
 {
-    using C = TileCfg<DIM, POLY>;
+    using C = QuadCfg<DIM, POLY>;
 #pragma unroll
     for (int iz = 0; iz < (DIM == 3 ? 3 : 1); ++iz) {
 #pragma unroll
@@ -261,91 +298,85 @@ __device__ __forceinline__ bool lds_hits(const PassArgs &a, const double *sx, co
     return false;
 }
 
-struct TileLattice {
-    int32_t h[3];      // colour cells per axis
-    int32_t off[3];    // parity offset per axis
-    int32_t nt[3];     // tiles per axis
-    int32_t tiles;     // total tiles
-    int32_t per_xcd;   // tiles per XCD chunk (ceil(tiles / 8))
-};
-
 template <int DIM, bool POLY>
-__global__ void __launch_bounds__(64) k_migrate_tile(PassArgs a, TileLattice L)
+__global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
 {
-    using C = TileCfg<DIM, POLY>;
+    using C = QuadCfg<DIM, POLY>;
     __shared__ double sx[C::kCap];
     __shared__ double sy[C::kCap];
     __shared__ double sz[DIM == 3 ? C::kCap : 1];
     __shared__ double srho[POLY ? C::kCap : 1];
     __shared__ int32_t lst[C::kCells + 1];
+    __shared__ uint16_t nearl[64][C::kNear];
+    __shared__ int32_t wtot[4];
 
     // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous
     // run of tiles so neighbouring tiles share its L2.
     const int32_t b = blockIdx.x;
     const int32_t tile = (b & 7) * L.per_xcd + (b >> 3);
     if (tile >= L.tiles) return;
-    const int32_t tx = tile % L.nt[0];
-    const int32_t ty = (tile / L.nt[0]) % L.nt[1];
-    const int32_t tz = (DIM == 3) ? tile / (L.nt[0] * L.nt[1]) : 0;
-    const int lane = threadIdx.x;
+    int32_t tx, ty, tz;
+    tile_coords<DIM>(L, tile, tx, ty, tz);
+    const int tid = threadIdx.x;
     const int32_t na0 = a.g.na[0], na1 = a.g.na[1], na2 = a.g.na[2];
-    // global cell of region cell 0 (one cell below the tile's first cell)
+    // global cell of region cell (0, 0, 0): one cell below the tile's first
     const int32_t ox = 2 * C::T * tx + L.off[0] - 1;
     const int32_t oy = 2 * C::T * ty + L.off[1] - 1;
     const int32_t oz = (DIM == 3) ? 2 * C::T * tz + L.off[2] - 1 : 0;
 
-    // 1. counts of the region cells and their global starts
-    int32_t gs[C::kPer];
+    // 1. particle counts of the region cells (thread owns cells r = C::kPer*tid + j)
+    int32_t gs[C::kPer], cn[C::kPer];
+    int32_t mine = 0;
 #pragma unroll
     for (int j = 0; j < C::kPer; ++j) {
-        const int32_t r = lane + 64 * j;
+        const int32_t r = C::kPer * tid + j;
         gs[j] = 0;
+        cn[j] = 0;
         if (r < C::kCells) {
             const int32_t rx = r % C::R, ry = (r / C::R) % C::R;
             const int32_t rz = (DIM == 3) ? r / (C::R * C::R) : 0;
             const int32_t gx = wrap_index(ox + rx, na0), gy = wrap_index(oy + ry, na1);
             const int32_t gz = (DIM == 3) ? wrap_index(oz + rz, na2) : 0;
             const int32_t gc = gx + na0 * (gy + na1 * gz);
-            const int32_t g0 = a.start[gc];
-            gs[j] = g0;
-            lst[r] = a.start[gc + 1] - g0;
+            gs[j] = a.start[gc];
+            cn[j] = a.start[gc + 1] - gs[j];
+            mine += cn[j];
         }
     }
+    // 2. block exclusive scan -> local CSR starts
+    const int32_t inc = wave_inclusive_scan(mine);
+    if ((tid & 63) == 63) wtot[tid >> 6] = inc;
     __syncthreads();
-    // 2. exclusive scan -> local CSR starts
-    int32_t carry = 0;
-    for (int base = 0; base < C::kCells; base += 64) {
-        const int32_t r = base + lane;
-        const int32_t v = (r < C::kCells) ? lst[r] : 0;
-        const int32_t inc = wave_inclusive_scan(v);
-        if (r < C::kCells) lst[r] = carry + inc - v;
-        carry += __shfl(inc, 63, 64);
+    int32_t off = inc - mine, total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int32_t t_ = wtot[w];
+        if (w < (tid >> 6)) off += t_;
+        total += t_;
     }
-    if (lane == 0) lst[C::kCells] = carry;
-    __syncthreads();
-
-    // own colour cell of this lane
-    const int32_t lx = lane % C::T;
-    const int32_t ly = (lane / C::T) % C::T;
-    const int32_t lz = (DIM == 3) ? lane / (C::T * C::T) : 0;
-    const int32_t jx = C::T * tx + lx, jy = C::T * ty + ly, jz = (DIM == 3) ? C::T * tz + lz : 0;
-    const bool active = jx < L.h[0] && jy < L.h[1] && (DIM == 2 || jz < L.h[2]) &&
-                        (DIM == 3 || lane < C::T * C::T);
-    const int32_t cx = 2 * jx + L.off[0], cy = 2 * jy + L.off[1];
-    const int32_t cz = (DIM == 3) ? 2 * jz + L.off[2] : 0;
-
-    if (carry > C::kCap) {
-        // 3'. over capacity: global-memory path for this tile
-        if (active) migrate_cell_global<DIM, POLY>(a, cx, cy, cz);
-        return;
-    }
-    // 3. stage positions: lane copies whole cells
 #pragma unroll
     for (int j = 0; j < C::kPer; ++j) {
-        const int32_t r = lane + 64 * j;
+        const int32_t r = C::kPer * tid + j;
+        if (r < C::kCells) lst[r] = off;
+        off += cn[j];
+    }
+    if (tid == 0) lst[C::kCells] = total;
+    if (total > C::kCap) {
+        // over capacity: the global-memory kernel takes this tile
+        if (tid == 0) {
+            const int32_t slot = atomicAdd(&L.ovf[L.colour], 1);
+            L.ovf[8 + L.colour * L.max_tiles + slot] = tile;
+        }
+        return;
+    }
+    // 3. stage positions
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < C::kPer; ++j) {
+        const int32_t r = C::kPer * tid + j;
         if (r < C::kCells) {
-            const int32_t d0 = lst[r], n = lst[r + 1] - d0, g0 = gs[j];
-            for (int32_t k = 0; k < n; ++k) {
+            const int32_t d0 = lst[r], g0 = gs[j];
+            for (int32_t k = 0; k < cn[j]; ++k) {
                 sx[d0 + k] = a.buf.x[0][g0 + k];
                 sy[d0 + k] = a.buf.x[1][g0 + k];
                 if (DIM == 3) sz[d0 + k] = a.buf.x[2][g0 + k];
@@ -354,49 +385,155 @@ __global__ void __launch_bounds__(64) k_migrate_tile(PassArgs a, TileLattice L)
         }
     }
     __syncthreads();
-    if (!active) return;
 
-    // 4. Algorithm 3 for the lane's cell against the LDS copy
+    // 4. quad q owns colour cell (lx, ly, lz) of the tile
+    const int q = tid >> 2, sub = tid & 3;
+    const int32_t lx = q % C::T, ly = (q / C::T) % C::T;
+    const int32_t lz = (DIM == 3) ? q / (C::T * C::T) : 0;
+    const int32_t jx = C::T * tx + lx, jy = C::T * ty + ly, jz = (DIM == 3) ? C::T * tz + lz : 0;
+    const bool active = jx < L.h[0] && jy < L.h[1] && (DIM == 2 || jz < L.h[2]);
+    if (!active) return;
+    const int32_t cx = 2 * jx + L.off[0], cy = 2 * jy + L.off[1];
+    const int32_t cz = (DIM == 3) ? 2 * jz + L.off[2] : 0;
     const int32_t rx = 2 * lx + 1, ry = 2 * ly + 1, rz = (DIM == 3) ? 2 * lz + 1 : 0;
     const int32_t ro = rx + C::R * (ry + C::R * rz);
     const int32_t lb = lst[ro], le = lst[ro + 1];
     if (lb == le) return;
     const int32_t gb = a.start[cx + na0 * (cy + na1 * cz)];
     const bool general = !is_interior<DIM>(a.g, cx, cy, cz);
-    double *__restrict__ X = a.buf.x[0];
-    double *__restrict__ Y = a.buf.x[1];
-    double *__restrict__ Z = a.buf.x[2];
+    const double margin = 2.0 * a.c_m;
+    uint16_t *const nl = nearl[q];
+
     for (int32_t p = lb; p < le; ++p) {
         const int32_t gp = gb + (p - lb);
         const double px = sx[p], py = sy[p], pz = (DIM == 3) ? sz[p] : 0.0;
-        const uint32_t id = (uint32_t)a.buf.id[gp];
         const double Ri = POLY ? a.s * srho[p] : a.s;
+        // near list: candidates within (R_i + R_j) + 2 c_m of the old position
+        int32_t nn = 0;
+#pragma unroll
+        for (int iz = 0; iz < (DIM == 3 ? 3 : 1); ++iz) {
+#pragma unroll
+            for (int iy = 0; iy < 3; ++iy) {
+                const int32_t row =
+                    (ry + iy - 1) * C::R + ((DIM == 3) ? (rz + iz - 1) * C::R * C::R : 0);
+                const int32_t lo = lst[row + rx - 1], hi = lst[row + rx + 2];
+                for (int32_t c0 = lo; c0 < hi; c0 += 4) {
+                    const int32_t c = c0 + sub;
+                    bool keep = false;
+                    if (c < hi && c != p) {
+                        double dx = px - sx[c], dy = py - sy[c];
+                        if (general) {
+                            dx = min_image(dx, a.g.box[0], a.g.half[0]);
+                            dy = min_image(dy, a.g.box[1], a.g.half[1]);
+                        }
+                        double qq = dx * dx + dy * dy;
+                        if (DIM == 3) {
+                            double dz = pz - sz[c];
+                            if (general) dz = min_image(dz, a.g.box[2], a.g.half[2]);
+                            qq = qq + dz * dz;
+                        }
+                        const double reach = (POLY ? Ri + a.s * srho[c] : Ri + Ri) + margin;
+                        keep = qq <= reach * reach;
+                    }
+                    const uint32_t qb = quad_bits(__ballot(keep));
+                    if (keep) {
+                        const int32_t slot = nn + __popc(qb & ((1u << sub) - 1u));
+                        if (slot < C::kNear) nl[slot] = (uint16_t)c;
+                    }
+                    nn += __popc(qb);
+                }
+            }
+        }
+        // trials in batches of four, one per lane of the quad
+        const uint32_t id = (uint32_t)a.buf.id[gp];
         uint8_t code = 0;
         Draw d = a.draw;
-        for (int32_t l = 1; l <= a.n_l; ++l) {
-            double v[3];
-            d.word = a.draw.word | ((uint32_t)l << 8);
-            unit_vector<DIM>(d, id, 0, a.c_m, v);
-            const double yx = wrap_coord(px + v[0], a.g.box[0]);
-            const double yy = wrap_coord(py + v[1], a.g.box[1]);
-            const double yz = (DIM == 3) ? wrap_coord(pz + v[2], a.g.box[2]) : 0.0;
-            const bool hit =
-                general ? lds_hits<DIM, POLY, true>(a, sx, sy, sz, srho, lst, rx, ry, rz, p, yx, yy,
-                                                    yz, Ri)
-                        : lds_hits<DIM, POLY, false>(a, sx, sy, sz, srho, lst, rx, ry, rz, p, yx,
-                                                     yy, yz, Ri);
-            if (!hit) {
-                sx[p] = yx;
-                sy[p] = yy;
-                if (DIM == 3) sz[p] = yz;
-                X[gp] = yx;
-                Y[gp] = yy;
-                if (DIM == 3) Z[gp] = yz;
-                code = (uint8_t)l;
+        for (int32_t base = 1; base <= a.n_l; base += 4) {
+            const int32_t l = base + sub;
+            bool free_ = false;
+            double yx = 0.0, yy = 0.0, yz = 0.0;
+            if (l <= a.n_l) {
+                double v[3];
+                d.word = a.draw.word | ((uint32_t)l << 8);
+                unit_vector<DIM>(d, id, 0, a.c_m, v);
+                yx = wrap_coord(px + v[0], a.g.box[0]);
+                yy = wrap_coord(py + v[1], a.g.box[1]);
+                yz = (DIM == 3) ? wrap_coord(pz + v[2], a.g.box[2]) : 0.0;
+                bool hit = false;
+                if (nn <= C::kNear) {
+                    for (int32_t e = 0; e < nn && !hit; ++e) {
+                        const int32_t c = nl[e];
+                        double dx = yx - sx[c], dy = yy - sy[c];
+                        if (general) {
+                            dx = min_image(dx, a.g.box[0], a.g.half[0]);
+                            dy = min_image(dy, a.g.box[1], a.g.half[1]);
+                        }
+                        double qq = dx * dx + dy * dy;
+                        if (DIM == 3) {
+                            double dz = yz - sz[c];
+                            if (general) dz = min_image(dz, a.g.box[2], a.g.half[2]);
+                            qq = qq + dz * dz;
+                        }
+                        double sig2;
+                        if (POLY) {
+                            const double sig = Ri + a.s * srho[c];
+                            sig2 = sig * sig;
+                        } else {
+                            sig2 = a.sig2_mono;
+                        }
+                        hit = qq <= sig2;
+                    }
+                } else {
+                    hit = general ? lds_hits<DIM, POLY, true>(a, sx, sy, sz, srho, lst, rx, ry,
+                                                              rz, p, yx, yy, yz, Ri)
+                                  : lds_hits<DIM, POLY, false>(a, sx, sy, sz, srho, lst, rx, ry,
+                                                               rz, p, yx, yy, yz, Ri);
+                }
+                free_ = !hit;
+            }
+            const uint32_t fb = quad_bits(__ballot(free_));
+            if (fb) {
+                const int win = __ffs(fb) - 1;
+                if (sub == win) {
+                    sx[p] = yx;
+                    sy[p] = yy;
+                    if (DIM == 3) sz[p] = yz;
+                    a.buf.x[0][gp] = yx;
+                    a.buf.x[1][gp] = yy;
+                    if (DIM == 3) a.buf.x[2][gp] = yz;
+                }
+                code = (uint8_t)(base + win);
                 break;
             }
         }
-        a.acc[gp] = code;
+        if (sub == 0) a.acc[gp] = code;
+        // the winner's LDS store must be seen by the quad's next particle
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// Tiles queued by k_migrate_tile because their neighbourhood exceeds LDS:
+// one thread per colour cell, candidates read from global memory.
+template <int DIM, bool POLY>
+__global__ void __launch_bounds__(64) k_migrate_overflow(PassArgs a, TileLattice L)
+{
+    using C = QuadCfg<DIM, POLY>;
+    const int32_t count = L.ovf[L.colour];
+    const int32_t *list = L.ovf + 8 + L.colour * L.max_tiles;
+    for (int32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const int32_t tile = list[i];
+        int32_t tx, ty, tz;
+        tile_coords<DIM>(L, tile, tx, ty, tz);
+        const int q = threadIdx.x;
+        const int32_t lx = q % C::T, ly = (q / C::T) % C::T;
+        const int32_t lz = (DIM == 3) ? q / (C::T * C::T) : 0;
+        const int32_t jx = C::T * tx + lx, jy = C::T * ty + ly;
+        const int32_t jz = (DIM == 3) ? C::T * tz + lz : 0;
+        if (jx < L.h[0] && jy < L.h[1] && (DIM == 2 || jz < L.h[2]))
+            migrate_cell_global<DIM, POLY>(a, 2 * jx + L.off[0], 2 * jy + L.off[1],
+                                           (DIM == 3) ? 2 * jz + L.off[2] : 0);
     }
 }
 
@@ -581,7 +718,7 @@ hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int 
     ColourLattice L;
     *launched = false;
     if (!colour_lattice(dim, a.g, colour, L)) return hipSuccess;
-    if (shape != SRM_PLATELET && tile_ok(dim, a.g)) {
+    if (shape != SRM_PLATELET && a.ovf && tile_ok(dim, a.g)) {
         TileLattice T{};
         const int tsz = (dim == 3) ? 4 : 8;
         T.tiles = 1;
@@ -591,17 +728,33 @@ hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int 
             T.nt[ax] = (ax < dim) ? (L.h[ax] + tsz - 1) / tsz : 1;
             T.tiles *= T.nt[ax];
         }
-        T.per_xcd = (T.tiles + 7) / 8;
-        const dim3 grid(8 * T.per_xcd), block(64);
-        if (dim == 3) {
-            if (poly) hipLaunchKernelGGL((k_migrate_tile<3, true>), grid, block, 0, stream, a, T);
-            else hipLaunchKernelGGL((k_migrate_tile<3, false>), grid, block, 0, stream, a, T);
-        } else {
-            if (poly) hipLaunchKernelGGL((k_migrate_tile<2, true>), grid, block, 0, stream, a, T);
-            else hipLaunchKernelGGL((k_migrate_tile<2, false>), grid, block, 0, stream, a, T);
+        if (T.tiles <= a.ovf_max_tiles) {
+            T.per_xcd = (T.tiles + 7) / 8;
+            T.colour = colour;
+            T.ovf = a.ovf;
+            T.max_tiles = a.ovf_max_tiles;
+            const dim3 grid(8 * T.per_xcd), block(256);
+            const dim3 ogrid(T.tiles < 512 ? T.tiles : 512), oblock(64);
+            if (dim == 3) {
+                if (poly) {
+                    hipLaunchKernelGGL((k_migrate_tile<3, true>), grid, block, 0, stream, a, T);
+                    hipLaunchKernelGGL((k_migrate_overflow<3, true>), ogrid, oblock, 0, stream, a, T);
+                } else {
+                    hipLaunchKernelGGL((k_migrate_tile<3, false>), grid, block, 0, stream, a, T);
+                    hipLaunchKernelGGL((k_migrate_overflow<3, false>), ogrid, oblock, 0, stream, a, T);
+                }
+            } else {
+                if (poly) {
+                    hipLaunchKernelGGL((k_migrate_tile<2, true>), grid, block, 0, stream, a, T);
+                    hipLaunchKernelGGL((k_migrate_overflow<2, true>), ogrid, oblock, 0, stream, a, T);
+                } else {
+                    hipLaunchKernelGGL((k_migrate_tile<2, false>), grid, block, 0, stream, a, T);
+                    hipLaunchKernelGGL((k_migrate_overflow<2, false>), ogrid, oblock, 0, stream, a, T);
+                }
+            }
+            *launched = true;
+            return hipGetLastError();
         }
-        *launched = true;
-        return hipGetLastError();
     }
     const dim3 grid(blocks_for(L.count)), block(kBlock);
     if (shape == SRM_PLATELET) {

@@ -63,6 +63,8 @@ struct srm_ctx {
     Counters *hcnt = nullptr;  // pinned
     double *dtmp = nullptr;    // 3n doubles: id-order staging
     int32_t *itmp = nullptr;   // n ints
+    int32_t *ovf = nullptr;    // tiled migration: 8 overflow counts + 8 tile lists
+    int32_t ovf_max_tiles = 0;
     int64_t ncap = 0;
     void *allocs[64];
     int nalloc = 0;
@@ -246,6 +248,8 @@ PassArgs pass_args(srm_ctx *c, const PBuf &b, const Grid &g, double s, int kind,
     a.n_l = c->p.n_l;
     a.c_m = c->p.c_m;
     a.c_n = c->p.c_n;
+    a.ovf = c->ovf;
+    a.ovf_max_tiles = c->ovf_max_tiles;
     return a;
 }
 
@@ -255,6 +259,7 @@ srm_status run_pass(srm_ctx *c, const PBuf &b, const Grid &g, double s, int kind
                     bool want_check, int32_t *ov, int64_t *nfail)
 {
     const PassArgs a = pass_args(c, b, g, s, kind, k);
+    HIP_TRY(launch_fill_i32(c->ovf, 8, 0, c->stream));
     hipEvent_t e0 = c->mark();
     for (int colour = 0; colour < (1 << c->dim); ++colour) {
         bool launched = false;
@@ -343,6 +348,17 @@ srm_status srm_init(const srm_params *p, const double *pos, const double *rho,
         (e = c->alloc(&c->acc, n)) || (e = c->alloc(&c->dtmp, 3 * n)) ||
         (e = c->alloc(&c->itmp, n)) || (e = c->alloc(&c->dcnt, 1)))
         return bail(fail(SRM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
+    {
+        // tiles per colour phase are at most prod_a ceil((ncap / 2) / T)
+        const int64_t tsz = (c->dim == 3) ? 4 : 8;
+        int64_t per = (c->ncap / 2 + tsz - 1) / tsz;
+        if (per < 1) per = 1;
+        int64_t mt = 1;
+        for (int a = 0; a < c->dim; ++a) mt *= per;
+        c->ovf_max_tiles = (int32_t)mt;
+        if ((e = c->alloc(&c->ovf, (size_t)(8 + 8 * mt))))
+            return bail(fail(SRM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
+    }
     c->sc.cap = (int64_t)n + 2;
     if ((e = c->alloc(&c->sc.counts, (size_t)c->sc.cap)) ||
         (e = c->alloc(&c->sc.start, (size_t)c->sc.cap + 1)) ||

@@ -74,6 +74,8 @@ struct PassArgs {
     Draw draw;         // key, sweep, kind<<31 | k<<16 (trial l added per draw)
     int32_t n_l;
     double c_m, c_n;
+    int32_t *ovf;          // tiled kernel: per-colour overflow counts + tile lists
+    int32_t ovf_max_tiles; // list capacity per colour
 };
 
 // One colour phase of a migration pass (Algorithm 3 over the cells whose
