@@ -166,6 +166,7 @@ __device__ __forceinline__ void migrate_cell_global(const PassArgs &a, int32_t c
             }
         }
         a.acc[p] = code;
+        if (code == 0) a.failed[1 + atomicAdd(&a.failed[0], 1)] = p;
     }
 }
 
@@ -190,20 +191,23 @@ __global__ void __launch_bounds__(kBlock) k_migrate_ball(PassArgs a, ColourLatti
 // (4x4x4 in 3D, 8x8 in 2D) and stages the (2T+1)^dim cells around them --
 // every cell its lanes can touch -- into LDS as SoA positions with a local
 // CSR index; each thread copies whole cells so neighbouring threads read
-// neighbouring addresses.  Four lanes (a quad) serve one cell and process
-// its particles in ascending id order:
-//  * the quad scans the 3^dim stencil once per particle and keeps the
-//    candidates whose distance to the particle's old position is at most
-//    R_i + R_j + 2 c_m (a superset of every particle a trial position within
-//    c_m of it can touch; the exact test below decides);
-//  * lane j of the quad draws trial l = base + j and tests it exactly
-//    against that short list; the lowest collision-free trial of the batch
-//    is accepted -- the first free trial of the sequential rule, since all
-//    trials of one particle are tested against the same neighbour state.
+// neighbouring addresses.  Then, with four lanes (a quad) per task:
+//  A. near lists, in parallel over all particles of the tile's own cells:
+//     the candidates of the 3^dim stencil outside the particle's own cell
+//     whose distance to its old position is at most R_i + R_j + 2 c_m.  No
+//     such candidate moves during this colour phase, and every particle a
+//     trial within c_m of the old position can touch is among them (the
+//     exact test decides).
+//  B. the sequential part, one quad per cell, particles in ascending id
+//     order: lane j of the quad draws trial l = base + j and tests it exactly
+//     against the near list and the other particles of its own cell at their
+//     current positions; the lowest collision-free trial of the batch is
+//     accepted -- the first free trial of the sequential rule, since all
+//     trials of one particle see the same neighbour state.
 // Accepted moves go to LDS (later particles of the cell see them) and HBM.
 // No quad reads a cell another quad writes (same colour), so LDS needs no
-// synchronisation after staging.  A tile whose neighbourhood does not fit
-// LDS is queued for the global-memory kernel.
+// synchronisation in phase B.  A tile whose neighbourhood does not fit LDS
+// is queued for the global-memory kernel.
 
 template <int DIM, bool POLY>
 struct QuadCfg {
@@ -212,9 +216,11 @@ struct QuadCfg {
     static constexpr int kCells = (DIM == 3) ? R * R * R : R * R;
     static constexpr int kThreads = 256;
     static constexpr int kPer = (kCells + kThreads - 1) / kThreads;
-    static constexpr int kNear = 16;
-    // LDS capacity in particles: ~40 KB per workgroup so four fit a CU.
-    static constexpr int kCap = (DIM == 3) ? (POLY ? 1088 : 1472) : (POLY ? 1536 : 2176);
+    static constexpr int kNear = 12;    // near-list entries per particle
+    static constexpr int kOwn = 160;    // particles of the tile's own cells
+    // LDS capacity in particles: the workgroup stays under 40 KB so four
+    // workgroups (sixteen waves) fit a CU.
+    static constexpr int kCap = (DIM == 3) ? (POLY ? 1088 : 1464) : (POLY ? 1472 : 2176);
 };
 
 struct TileLattice {
@@ -255,13 +261,33 @@ __device__ __forceinline__ void tile_coords(const TileLattice &L, int32_t tile, 
     tz = (DIM == 3) ? tile / (L.nt[0] * L.nt[1]) : 0;
 }
 
-// Candidate test against the LDS copy: the 3 (2D) or 9 (3D) rows of three
-// consecutive region cells around region cell (rx, ry, rz).
+// Squared distance (d0*d0 + d1*d1) + d2*d2 of two points, with the
+// minimum-image correction when GENERAL.
+template <int DIM, bool GENERAL>
+__device__ __forceinline__ double sq_dist(const Grid &g, double ax, double ay, double az,
+                                          double bx, double by, double bz)
+{
+    double dx = ax - bx, dy = ay - by;
+    if (GENERAL) {
+        dx = min_image(dx, g.box[0], g.half[0]);
+        dy = min_image(dy, g.box[1], g.half[1]);
+    }
+    double qq = dx * dx + dy * dy;
+    if (DIM == 3) {
+        double dz = az - bz;
+        if (GENERAL) dz = min_image(dz, g.box[2], g.half[2]);
+        qq = qq + dz * dz;
+    }
+    return qq;
+}
+
+// Exact contact test of a ball of radius Ri at y against every particle of
+// the 3^dim stencil of region cell (rx, ry, rz) except LDS slot `self`.
 template <int DIM, bool POLY, bool GENERAL>
 __device__ __forceinline__ bool lds_hits(const PassArgs &a, const double *sx, const double *sy,
-                                         const double *sz, const double *srho, const int32_t *lst,
-                                         int32_t rx, int32_t ry, int32_t rz, int32_t self,
-                                         double yx, double yy, double yz, double Ri)
+                                         const double *sz, const double *srho,
+                                         const uint16_t *lst, int32_t rx, int32_t ry, int32_t rz,
+                                         int32_t self, double yx, double yy, double yz, double Ri)
 {
     using C = QuadCfg<DIM, POLY>;
 #pragma unroll
@@ -272,18 +298,8 @@ __device__ __forceinline__ bool lds_hits(const PassArgs &a, const double *sx, co
             const int32_t lo = lst[row + rx - 1], hi = lst[row + rx + 2];
             for (int32_t q = lo; q < hi; ++q) {
                 if (q == self) continue;
-                double dx = yx - sx[q];
-                double dy = yy - sy[q];
-                if (GENERAL) {
-                    dx = min_image(dx, a.g.box[0], a.g.half[0]);
-                    dy = min_image(dy, a.g.box[1], a.g.half[1]);
-                }
-                double qq = dx * dx + dy * dy;
-                if (DIM == 3) {
-                    double dz = yz - sz[q];
-                    if (GENERAL) dz = min_image(dz, a.g.box[2], a.g.half[2]);
-                    qq = qq + dz * dz;
-                }
+                const double qq = sq_dist<DIM, GENERAL>(a.g, yx, yy, yz, sx[q], sy[q],
+                                                        (DIM == 3) ? sz[q] : 0.0);
                 double sig2;
                 if (POLY) {
                     const double sig = Ri + a.s * srho[q];
@@ -298,6 +314,89 @@ __device__ __forceinline__ bool lds_hits(const PassArgs &a, const double *sx, co
     return false;
 }
 
+// Phase A for the particle in LDS slot p of own cell [ob, oe): the quad's
+// lanes split the stencil's candidates four ways and append the near ones
+// to nl; *count gets their number, or 255 when nl overflowed.
+template <int DIM, bool POLY, bool GENERAL>
+__device__ __forceinline__ void build_near(const PassArgs &a, const double *sx, const double *sy,
+                                           const double *sz, const double *srho,
+                                           const uint16_t *lst, int32_t rx, int32_t ry,
+                                           int32_t rz, int32_t ob, int32_t oe, int32_t p,
+                                           uint16_t *nl, uint8_t *count, int sub)
+{
+    using C = QuadCfg<DIM, POLY>;
+    const double px = sx[p], py = sy[p], pz = (DIM == 3) ? sz[p] : 0.0;
+    const double Ri = POLY ? a.s * srho[p] : a.s;
+    const double margin = 2.0 * a.c_m;
+    int32_t nn = 0;
+#pragma unroll
+    for (int iz = 0; iz < (DIM == 3 ? 3 : 1); ++iz) {
+#pragma unroll
+        for (int iy = 0; iy < 3; ++iy) {
+            const int32_t row = (ry + iy - 1) * C::R + ((DIM == 3) ? (rz + iz - 1) * C::R * C::R : 0);
+            const int32_t lo = lst[row + rx - 1], hi = lst[row + rx + 2];
+            for (int32_t c0 = lo; c0 < hi; c0 += 4) {
+                const int32_t c = c0 + sub;
+                bool keep = false;
+                if (c < hi && (c < ob || c >= oe)) {
+                    const double qq = sq_dist<DIM, GENERAL>(a.g, px, py, pz, sx[c], sy[c],
+                                                            (DIM == 3) ? sz[c] : 0.0);
+                    const double reach = (POLY ? Ri + a.s * srho[c] : Ri + Ri) + margin;
+                    keep = qq <= reach * reach;
+                }
+                const uint32_t qb = quad_bits(__ballot(keep));
+                if (keep) {
+                    const int32_t slot = nn + __popc(qb & ((1u << sub) - 1u));
+                    if (slot < C::kNear) nl[slot] = (uint16_t)c;
+                }
+                nn += __popc(qb);
+            }
+        }
+    }
+    if (sub == 0) *count = (uint8_t)(nn > C::kNear ? 255 : nn);
+}
+
+// Phase B test of one trial position y of the particle in LDS slot p.
+template <int DIM, bool POLY, bool GENERAL>
+__device__ __forceinline__ bool trial_hits(const PassArgs &a, const double *sx, const double *sy,
+                                           const double *sz, const double *srho,
+                                           const uint16_t *lst, const uint16_t *nl, int32_t nn,
+                                           int32_t rx, int32_t ry, int32_t rz, int32_t ob,
+                                           int32_t oe, int32_t p, double yx, double yy,
+                                           double yz, double Ri)
+{
+    if (nn == 255)
+        return lds_hits<DIM, POLY, GENERAL>(a, sx, sy, sz, srho, lst, rx, ry, rz, p, yx, yy, yz,
+                                            Ri);
+    for (int32_t e = 0; e < nn; ++e) {
+        const int32_t c = nl[e];
+        const double qq = sq_dist<DIM, GENERAL>(a.g, yx, yy, yz, sx[c], sy[c],
+                                                (DIM == 3) ? sz[c] : 0.0);
+        double sig2;
+        if (POLY) {
+            const double sig = Ri + a.s * srho[c];
+            sig2 = sig * sig;
+        } else {
+            sig2 = a.sig2_mono;
+        }
+        if (qq <= sig2) return true;
+    }
+    for (int32_t c = ob; c < oe; ++c) {
+        if (c == p) continue;
+        const double qq = sq_dist<DIM, GENERAL>(a.g, yx, yy, yz, sx[c], sy[c],
+                                                (DIM == 3) ? sz[c] : 0.0);
+        double sig2;
+        if (POLY) {
+            const double sig = Ri + a.s * srho[c];
+            sig2 = sig * sig;
+        } else {
+            sig2 = a.sig2_mono;
+        }
+        if (qq <= sig2) return true;
+    }
+    return false;
+}
+
 template <int DIM, bool POLY>
 __global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
 {
@@ -306,8 +405,10 @@ __global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
     __shared__ double sy[C::kCap];
     __shared__ double sz[DIM == 3 ? C::kCap : 1];
     __shared__ double srho[POLY ? C::kCap : 1];
-    __shared__ int32_t lst[C::kCells + 1];
-    __shared__ uint16_t nearl[64][C::kNear];
+    __shared__ uint16_t lst[C::kCells + 1];
+    __shared__ uint16_t obase[65];
+    __shared__ uint16_t nearl[C::kOwn][C::kNear];
+    __shared__ uint8_t ncnt[C::kOwn];
     __shared__ int32_t wtot[4];
 
     // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous
@@ -324,7 +425,7 @@ __global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
     const int32_t oy = 2 * C::T * ty + L.off[1] - 1;
     const int32_t oz = (DIM == 3) ? 2 * C::T * tz + L.off[2] - 1 : 0;
 
-    // 1. particle counts of the region cells (thread owns cells r = C::kPer*tid + j)
+    // 1. particle counts of the region cells (thread owns cells r = kPer*tid + j)
     int32_t gs[C::kPer], cn[C::kPer];
     int32_t mine = 0;
 #pragma unroll
@@ -354,13 +455,6 @@ __global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
         if (w < (tid >> 6)) off += t_;
         total += t_;
     }
-#pragma unroll
-    for (int j = 0; j < C::kPer; ++j) {
-        const int32_t r = C::kPer * tid + j;
-        if (r < C::kCells) lst[r] = off;
-        off += cn[j];
-    }
-    if (tid == 0) lst[C::kCells] = total;
     if (total > C::kCap) {
         // over capacity: the global-memory kernel takes this tile
         if (tid == 0) {
@@ -369,82 +463,134 @@ __global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
         }
         return;
     }
-    // 3. stage positions
-    __syncthreads();
 #pragma unroll
     for (int j = 0; j < C::kPer; ++j) {
         const int32_t r = C::kPer * tid + j;
-        if (r < C::kCells) {
-            const int32_t d0 = lst[r], g0 = gs[j];
-            for (int32_t k = 0; k < cn[j]; ++k) {
+        if (r < C::kCells) lst[r] = (uint16_t)off;
+        off += cn[j];
+    }
+    if (tid == 0) lst[C::kCells] = (uint16_t)total;
+
+    // 3. stage positions: the first three particles of each of the thread's
+    // cells are loaded together (one memory round trip), the rest after
+    {
+        double vx[C::kPer][3], vy[C::kPer][3], vz[C::kPer][3], vr[C::kPer][3];
+#pragma unroll
+        for (int j = 0; j < C::kPer; ++j) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (k < cn[j]) {
+                    vx[j][k] = a.buf.x[0][gs[j] + k];
+                    vy[j][k] = a.buf.x[1][gs[j] + k];
+                    if (DIM == 3) vz[j][k] = a.buf.x[2][gs[j] + k];
+                    if (POLY) vr[j][k] = a.buf.rho[gs[j] + k];
+                }
+            }
+        }
+        int32_t d = off;
+#pragma unroll
+        for (int j = C::kPer - 1; j >= 0; --j) d -= cn[j];
+#pragma unroll
+        for (int j = 0; j < C::kPer; ++j) {
+            const int32_t d0 = d, g0 = gs[j];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (k < cn[j]) {
+                    sx[d0 + k] = vx[j][k];
+                    sy[d0 + k] = vy[j][k];
+                    if (DIM == 3) sz[d0 + k] = vz[j][k];
+                    if (POLY) srho[d0 + k] = vr[j][k];
+                }
+            }
+            for (int32_t k = 3; k < cn[j]; ++k) {
                 sx[d0 + k] = a.buf.x[0][g0 + k];
                 sy[d0 + k] = a.buf.x[1][g0 + k];
                 if (DIM == 3) sz[d0 + k] = a.buf.x[2][g0 + k];
                 if (POLY) srho[d0 + k] = a.buf.rho[g0 + k];
             }
+            d += cn[j];
         }
     }
     __syncthreads();
 
-    // 4. quad q owns colour cell (lx, ly, lz) of the tile
+    // 4. own cells: slot k of the tile -> particles obase[k] .. obase[k+1]
     const int q = tid >> 2, sub = tid & 3;
-    const int32_t lx = q % C::T, ly = (q / C::T) % C::T;
-    const int32_t lz = (DIM == 3) ? q / (C::T * C::T) : 0;
-    const int32_t jx = C::T * tx + lx, jy = C::T * ty + ly, jz = (DIM == 3) ? C::T * tz + lz : 0;
-    const bool active = jx < L.h[0] && jy < L.h[1] && (DIM == 2 || jz < L.h[2]);
+    auto own_cell = [&](int k, int32_t &lx_, int32_t &ly_, int32_t &lz_, bool &act_) {
+        lx_ = k % C::T;
+        ly_ = (k / C::T) % C::T;
+        lz_ = (DIM == 3) ? k / (C::T * C::T) : 0;
+        act_ = C::T * tx + lx_ < L.h[0] && C::T * ty + ly_ < L.h[1] &&
+               (DIM == 2 || C::T * tz + lz_ < L.h[2]);
+    };
+    auto region_index = [&](int32_t lx_, int32_t ly_, int32_t lz_) {
+        return (2 * lx_ + 1) + C::R * ((2 * ly_ + 1) + C::R * ((DIM == 3) ? 2 * lz_ + 1 : 0));
+    };
+    if (tid < 64) {
+        int32_t lx_, ly_, lz_;
+        bool act_;
+        own_cell(tid, lx_, ly_, lz_, act_);
+        const int32_t ro_ = region_index(lx_, ly_, lz_);
+        const int32_t m_ = act_ ? (int32_t)lst[ro_ + 1] - (int32_t)lst[ro_] : 0;
+        const int32_t incl = wave_inclusive_scan(m_);
+        obase[tid] = (uint16_t)(incl - m_);
+        if (tid == 63) obase[64] = (uint16_t)(incl > 65535 ? 65535 : incl);
+    }
+    __syncthreads();
+    const int32_t nown = obase[64];
+    const bool use_near = nown <= C::kOwn;
+
+    // 5. phase A: near lists for every own particle (quad per particle)
+    if (use_near) {
+        for (int32_t o = q; o < nown; o += 64) {
+            int32_t klo = 0, khi = 63;
+            while (klo < khi) {
+                const int32_t mid = (klo + khi + 1) >> 1;
+                if (obase[mid] <= o) klo = mid;
+                else khi = mid - 1;
+            }
+            int32_t lx_, ly_, lz_;
+            bool act_;
+            own_cell(klo, lx_, ly_, lz_, act_);
+            const int32_t ro_ = region_index(lx_, ly_, lz_);
+            const int32_t ob = lst[ro_], oe = lst[ro_ + 1];
+            const int32_t p = ob + (o - obase[klo]);
+            const int32_t cx_ = 2 * (C::T * tx + lx_) + L.off[0];
+            const int32_t cy_ = 2 * (C::T * ty + ly_) + L.off[1];
+            const int32_t cz_ = (DIM == 3) ? 2 * (C::T * tz + lz_) + L.off[2] : 0;
+            const int32_t rx_ = 2 * lx_ + 1, ry_ = 2 * ly_ + 1, rz_ = (DIM == 3) ? 2 * lz_ + 1 : 0;
+            if (is_interior<DIM>(a.g, cx_, cy_, cz_))
+                build_near<DIM, POLY, false>(a, sx, sy, sz, srho, lst, rx_, ry_, rz_, ob, oe, p,
+                                             nearl[o], &ncnt[o], sub);
+            else
+                build_near<DIM, POLY, true>(a, sx, sy, sz, srho, lst, rx_, ry_, rz_, ob, oe, p,
+                                            nearl[o], &ncnt[o], sub);
+        }
+    }
+    __syncthreads();
+
+    // 6. phase B: quad q runs its cell's particles in ascending id order
+    int32_t lx, ly, lz;
+    bool active;
+    own_cell(q, lx, ly, lz, active);
     if (!active) return;
-    const int32_t cx = 2 * jx + L.off[0], cy = 2 * jy + L.off[1];
-    const int32_t cz = (DIM == 3) ? 2 * jz + L.off[2] : 0;
     const int32_t rx = 2 * lx + 1, ry = 2 * ly + 1, rz = (DIM == 3) ? 2 * lz + 1 : 0;
-    const int32_t ro = rx + C::R * (ry + C::R * rz);
-    const int32_t lb = lst[ro], le = lst[ro + 1];
-    if (lb == le) return;
+    const int32_t ro = region_index(lx, ly, lz);
+    const int32_t ob = lst[ro], oe = lst[ro + 1];
+    if (ob == oe) return;
+    const int32_t cx = 2 * (C::T * tx + lx) + L.off[0];
+    const int32_t cy = 2 * (C::T * ty + ly) + L.off[1];
+    const int32_t cz = (DIM == 3) ? 2 * (C::T * tz + lz) + L.off[2] : 0;
     const int32_t gb = a.start[cx + na0 * (cy + na1 * cz)];
     const bool general = !is_interior<DIM>(a.g, cx, cy, cz);
-    const double margin = 2.0 * a.c_m;
-    uint16_t *const nl = nearl[q];
+    const int32_t o0 = obase[q];
 
-    for (int32_t p = lb; p < le; ++p) {
-        const int32_t gp = gb + (p - lb);
+    for (int32_t p = ob; p < oe; ++p) {
+        const int32_t gp = gb + (p - ob);
+        const int32_t o = o0 + (p - ob);
         const double px = sx[p], py = sy[p], pz = (DIM == 3) ? sz[p] : 0.0;
         const double Ri = POLY ? a.s * srho[p] : a.s;
-        // near list: candidates within (R_i + R_j) + 2 c_m of the old position
-        int32_t nn = 0;
-#pragma unroll
-        for (int iz = 0; iz < (DIM == 3 ? 3 : 1); ++iz) {
-#pragma unroll
-            for (int iy = 0; iy < 3; ++iy) {
-                const int32_t row =
-                    (ry + iy - 1) * C::R + ((DIM == 3) ? (rz + iz - 1) * C::R * C::R : 0);
-                const int32_t lo = lst[row + rx - 1], hi = lst[row + rx + 2];
-                for (int32_t c0 = lo; c0 < hi; c0 += 4) {
-                    const int32_t c = c0 + sub;
-                    bool keep = false;
-                    if (c < hi && c != p) {
-                        double dx = px - sx[c], dy = py - sy[c];
-                        if (general) {
-                            dx = min_image(dx, a.g.box[0], a.g.half[0]);
-                            dy = min_image(dy, a.g.box[1], a.g.half[1]);
-                        }
-                        double qq = dx * dx + dy * dy;
-                        if (DIM == 3) {
-                            double dz = pz - sz[c];
-                            if (general) dz = min_image(dz, a.g.box[2], a.g.half[2]);
-                            qq = qq + dz * dz;
-                        }
-                        const double reach = (POLY ? Ri + a.s * srho[c] : Ri + Ri) + margin;
-                        keep = qq <= reach * reach;
-                    }
-                    const uint32_t qb = quad_bits(__ballot(keep));
-                    if (keep) {
-                        const int32_t slot = nn + __popc(qb & ((1u << sub) - 1u));
-                        if (slot < C::kNear) nl[slot] = (uint16_t)c;
-                    }
-                    nn += __popc(qb);
-                }
-            }
-        }
-        // trials in batches of four, one per lane of the quad
+        const int32_t nn = use_near ? (int32_t)ncnt[o] : 255;
+        const uint16_t *nl = use_near ? nearl[o] : nullptr;
         const uint32_t id = (uint32_t)a.buf.id[gp];
         uint8_t code = 0;
         Draw d = a.draw;
@@ -459,36 +605,11 @@ __global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
                 yx = wrap_coord(px + v[0], a.g.box[0]);
                 yy = wrap_coord(py + v[1], a.g.box[1]);
                 yz = (DIM == 3) ? wrap_coord(pz + v[2], a.g.box[2]) : 0.0;
-                bool hit = false;
-                if (nn <= C::kNear) {
-                    for (int32_t e = 0; e < nn && !hit; ++e) {
-                        const int32_t c = nl[e];
-                        double dx = yx - sx[c], dy = yy - sy[c];
-                        if (general) {
-                            dx = min_image(dx, a.g.box[0], a.g.half[0]);
-                            dy = min_image(dy, a.g.box[1], a.g.half[1]);
-                        }
-                        double qq = dx * dx + dy * dy;
-                        if (DIM == 3) {
-                            double dz = yz - sz[c];
-                            if (general) dz = min_image(dz, a.g.box[2], a.g.half[2]);
-                            qq = qq + dz * dz;
-                        }
-                        double sig2;
-                        if (POLY) {
-                            const double sig = Ri + a.s * srho[c];
-                            sig2 = sig * sig;
-                        } else {
-                            sig2 = a.sig2_mono;
-                        }
-                        hit = qq <= sig2;
-                    }
-                } else {
-                    hit = general ? lds_hits<DIM, POLY, true>(a, sx, sy, sz, srho, lst, rx, ry,
-                                                              rz, p, yx, yy, yz, Ri)
-                                  : lds_hits<DIM, POLY, false>(a, sx, sy, sz, srho, lst, rx, ry,
-                                                               rz, p, yx, yy, yz, Ri);
-                }
+                const bool hit =
+                    general ? trial_hits<DIM, POLY, true>(a, sx, sy, sz, srho, lst, nl, nn, rx, ry,
+                                                          rz, ob, oe, p, yx, yy, yz, Ri)
+                            : trial_hits<DIM, POLY, false>(a, sx, sy, sz, srho, lst, nl, nn, rx,
+                                                           ry, rz, ob, oe, p, yx, yy, yz, Ri);
                 free_ = !hit;
             }
             const uint32_t fb = quad_bits(__ballot(free_));
@@ -506,7 +627,10 @@ __global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
                 break;
             }
         }
-        if (sub == 0) a.acc[gp] = code;
+        if (sub == 0) {
+            a.acc[gp] = code;
+            if (code == 0) a.failed[1 + atomicAdd(&a.failed[0], 1)] = gp;
+        }
         // the winner's LDS store must be seen by the quad's next particle
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -544,14 +668,8 @@ __global__ void __launch_bounds__(64) k_migrate_overflow(PassArgs a, TileLattice
 // So only particles with accept code 0 are tested; check_all tests every
 // particle (initial-state validation).
 template <int DIM, bool POLY>
-__global__ void __launch_bounds__(kBlock) k_check_ball(PassArgs a, int32_t check_all, Counters *cnt)
+__device__ __forceinline__ bool check_ball_one(const PassArgs &a, int32_t p)
 {
-    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool failed = (p < a.n) && (check_all || a.acc[p] == 0);
-    const unsigned long long m = __ballot(failed);
-    if ((threadIdx.x & 63) == 0 && m != 0ull)
-        atomicAdd((unsigned long long *)&cnt->nfail, (unsigned long long)__popcll(m));
-    if (!failed) return;
     const double x = a.buf.x[0][p], y = a.buf.x[1][p];
     const double z = (DIM == 3) ? a.buf.x[2][p] : 0.0;
     const int32_t cx = cell_coord(x, a.g.inv_w[0], a.g.na[0]);
@@ -560,8 +678,20 @@ __global__ void __launch_bounds__(kBlock) k_check_ball(PassArgs a, int32_t check
     int32_t lo[Rows<DIM>::kRanges], hi[Rows<DIM>::kRanges];
     stencil_slices<DIM>(a.g, a.start, cx, cy, cz, lo, hi);
     const double Ri = POLY ? a.s * a.buf.rho[p] : a.s;
-    if (ball_hits<DIM, POLY, true>(a, lo, hi, p, x, y, z, Ri)) atomicOr(&cnt->overlap, 1);
+    return ball_hits<DIM, POLY, true>(a, lo, hi, p, x, y, z, Ri);
 }
+
+template <int DIM, bool POLY>
+__global__ void __launch_bounds__(kBlock) k_check_ball(PassArgs a, int32_t check_all, Counters *cnt)
+{
+    const int32_t count = check_all ? a.n : a.failed[0];
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += gridDim.x * blockDim.x) {
+        const int32_t p = check_all ? i : a.failed[1 + i];
+        if (check_ball_one<DIM, POLY>(a, p)) atomicOr(&cnt->overlap, 1);
+    }
+}
+
 
 // ---------------------------------------------------------------- platelets
 
@@ -653,18 +783,12 @@ __global__ void __launch_bounds__(kBlock) k_migrate_platelet(PassArgs a, ColourL
             }
         }
         a.acc[p] = code;
+        if (code == 0) a.failed[1 + atomicAdd(&a.failed[0], 1)] = p;
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_check_platelet(PassArgs a, int32_t check_all,
-                                                           Counters *cnt)
+__device__ __forceinline__ bool check_platelet_one(const PassArgs &a, int32_t p)
 {
-    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool failed = (p < a.n) && (check_all || a.acc[p] == 0);
-    const unsigned long long m = __ballot(failed);
-    if ((threadIdx.x & 63) == 0 && m != 0ull)
-        atomicAdd((unsigned long long *)&cnt->nfail, (unsigned long long)__popcll(m));
-    if (!failed) return;
     const double x = a.buf.x[0][p], y = a.buf.x[1][p], z = a.buf.x[2][p];
     const double np_[3] = {a.buf.nrm[0][p], a.buf.nrm[1][p], a.buf.nrm[2][p]};
     const int32_t cx = cell_coord(x, a.g.inv_w[0], a.g.na[0]);
@@ -673,7 +797,18 @@ __global__ void __launch_bounds__(kBlock) k_check_platelet(PassArgs a, int32_t c
     int32_t lo[Rows<3>::kRanges], hi[Rows<3>::kRanges];
     stencil_slices<3>(a.g, a.start, cx, cy, cz, lo, hi);
     const double ai = a.buf.rho ? a.s * a.buf.rho[p] : a.s;
-    if (platelet_hits(a, lo, hi, p, a.buf.id[p], x, y, z, np_, ai)) atomicOr(&cnt->overlap, 1);
+    return platelet_hits(a, lo, hi, p, a.buf.id[p], x, y, z, np_, ai);
+}
+
+__global__ void __launch_bounds__(kBlock) k_check_platelet(PassArgs a, int32_t check_all,
+                                                           Counters *cnt)
+{
+    const int32_t count = check_all ? a.n : a.failed[0];
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += gridDim.x * blockDim.x) {
+        const int32_t p = check_all ? i : a.failed[1 + i];
+        if (check_platelet_one(a, p)) atomicOr(&cnt->overlap, 1);
+    }
 }
 
 inline unsigned blocks_for(int64_t n)
@@ -774,7 +909,9 @@ hipError_t check_overlaps(int dim, int shape, bool poly, const PassArgs &a, bool
                           Counters *cnt, hipStream_t stream)
 {
     if (a.n <= 0) return hipSuccess;
-    const dim3 grid(blocks_for(a.n)), block(kBlock);
+    // grid-stride over the failed list (its length is only known on the device)
+    const unsigned nb = blocks_for(a.n);
+    const dim3 grid(check_all ? nb : (nb < 1024 ? nb : 1024)), block(kBlock);
     const int32_t all = check_all ? 1 : 0;
     if (shape == SRM_PLATELET) {
         hipLaunchKernelGGL(k_check_platelet, grid, block, 0, stream, a, all, cnt);

@@ -64,6 +64,7 @@ struct srm_ctx {
     double *dtmp = nullptr;    // 3n doubles: id-order staging
     int32_t *itmp = nullptr;   // n ints
     int32_t *ovf = nullptr;    // tiled migration: 8 overflow counts + 8 tile lists
+    int32_t *failed = nullptr; // [0] count, then slots with accept code 0
     int32_t ovf_max_tiles = 0;
     int64_t ncap = 0;
     void *allocs[64];
@@ -250,6 +251,7 @@ PassArgs pass_args(srm_ctx *c, const PBuf &b, const Grid &g, double s, int kind,
     a.c_n = c->p.c_n;
     a.ovf = c->ovf;
     a.ovf_max_tiles = c->ovf_max_tiles;
+    a.failed = c->failed;
     return a;
 }
 
@@ -260,6 +262,7 @@ srm_status run_pass(srm_ctx *c, const PBuf &b, const Grid &g, double s, int kind
 {
     const PassArgs a = pass_args(c, b, g, s, kind, k);
     HIP_TRY(launch_fill_i32(c->ovf, 8, 0, c->stream));
+    HIP_TRY(launch_fill_i32(c->failed, 1, 0, c->stream));
     hipEvent_t e0 = c->mark();
     for (int colour = 0; colour < (1 << c->dim); ++colour) {
         bool launched = false;
@@ -282,10 +285,12 @@ srm_status run_pass(srm_ctx *c, const PBuf &b, const Grid &g, double s, int kind
     c->span(2, e2, c->mark());
     if (c->prof_on) c->prof.checks += 1;
     HIP_TRY(hipMemcpyAsync(c->hcnt, c->dcnt, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(&c->hcnt->nfail_list, c->failed, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->resolve();
     if (ov) *ov = c->hcnt->overlap;
-    if (nfail) *nfail = c->hcnt->nfail;
+    if (nfail) *nfail = c->hcnt->nfail_list;
     return SRM_OK;
 }
 
@@ -359,6 +364,8 @@ srm_status srm_init(const srm_params *p, const double *pos, const double *rho,
         if ((e = c->alloc(&c->ovf, (size_t)(8 + 8 * mt))))
             return bail(fail(SRM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
     }
+    if ((e = c->alloc(&c->failed, n + 1)))
+        return bail(fail(SRM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
     c->sc.cap = (int64_t)n + 2;
     if ((e = c->alloc(&c->sc.counts, (size_t)c->sc.cap)) ||
         (e = c->alloc(&c->sc.start, (size_t)c->sc.cap + 1)) ||

@@ -21,9 +21,11 @@ struct PBuf {
 
 // Small device-side result block of the global check.
 struct Counters {
-    int32_t overlap;   // 1 if a colliding particle was found
-    int32_t bad;       // 1 if an input coordinate was outside the box
-    int64_t nfail;     // particles with accept code 0
+    int32_t overlap;     // 1 if a colliding particle was found
+    int32_t bad;         // 1 if an input coordinate was outside the box
+    int64_t nfail;       // unused by the check kernels (kept for layout)
+    int32_t nfail_list;  // host copy of the failed-list length
+    int32_t pad;
 };
 
 struct Scratch {
@@ -76,6 +78,7 @@ struct PassArgs {
     double c_m, c_n;
     int32_t *ovf;          // tiled kernel: per-colour overflow counts + tile lists
     int32_t ovf_max_tiles; // list capacity per colour
+    int32_t *failed;       // [0] = count, then slots of particles that rejected every trial
 };
 
 // One colour phase of a migration pass (Algorithm 3 over the cells whose
