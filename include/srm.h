@@ -118,10 +118,13 @@ srm_status srm_sweep(srm_ctx *ctx, srm_sweep_info *info);
 srm_status srm_run_to_fraction(srm_ctx *ctx, int32_t max_sweeps, srm_run_info *info);
 
 /* Pairs i < j of the committed state (original ids) whose shapes come within
- * `gap` of each other: balls with q_ij <= ((R_i + R_j) + gap)^2 under the
- * minimum image; platelets (gap must be 0) whose disks intersect.  Written
- * to ij as (i, j) int32 pairs sorted by (i, j); *count = number of pairs.
- * SRM_ECAPACITY (nothing written) if *count > cap. */
+ * `gap` >= 0 of each other: balls with q_ij <= ((R_i + R_j) + gap)^2 under
+ * the minimum image (the hard core - soft shell contact of percolation
+ * studies, Sec. 3.3); platelets whose disks, with radii grown to a + gap/2,
+ * intersect (gap = 0: the admissibility test itself).  Written to ij (host
+ * or device per mem_kind) as (i, j) int32 pairs sorted by (i, j); *count =
+ * number of pairs (fewer than 2^31).  SRM_ECAPACITY (nothing written) if
+ * *count > cap. */
 srm_status srm_pairs(srm_ctx *ctx, double gap, int64_t cap, int32_t *ij, int64_t *count,
                      int32_t mem_kind);
 

@@ -43,9 +43,12 @@ __global__ void k_iota(int32_t *a, int32_t n)
     if (i < n) a[i] = i;
 }
 
-// Cell id of each particle, its rank in the cell by atomic increment, and a
-// range check of the coordinates (a coordinate outside [0, L) or NaN sets
-// cnt->bad and is binned into cell 0 so that every index stays in bounds).
+// Cell id of each particle, its rank in the cell, and a range check of the
+// coordinates (a coordinate outside [0, L) or NaN sets cnt->bad and is
+// binned into cell 0 so that every index stays in bounds).  The input is in
+// the previous cell order, so neighbouring lanes mostly share a cell: each
+// run of equal cells within a wavefront claims its slots with one atomic
+// add by its first lane.
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_bin_count(const double *__restrict__ x,
                                                       const double *__restrict__ y,
@@ -55,18 +58,33 @@ __global__ void __launch_bounds__(kBlock) k_bin_count(const double *__restrict__
                                                       int32_t *__restrict__ counts, Counters *cnt)
 {
     const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const double px = x[p], py = y[p], pz = (DIM == 3) ? z[p] : 0.0;
-    bool ok = (px >= 0.0 && px < g.box[0]) && (py >= 0.0 && py < g.box[1]);
-    if (DIM == 3) ok = ok && (pz >= 0.0 && pz < g.box[2]);
-    int32_t c = 0;
-    if (ok) {
-        c = cell_of<DIM>(g, px, py, pz);
-    } else {
-        cnt->bad = 1;
+    const bool live = p < n;
+    int32_t c = -1;
+    if (live) {
+        const double px = x[p], py = y[p], pz = (DIM == 3) ? z[p] : 0.0;
+        bool ok = (px >= 0.0 && px < g.box[0]) && (py >= 0.0 && py < g.box[1]);
+        if (DIM == 3) ok = ok && (pz >= 0.0 && pz < g.box[2]);
+        c = 0;
+        if (ok) c = cell_of<DIM>(g, px, py, pz);
+        else cnt->bad = 1;
     }
+    const int lane = threadIdx.x & 63;
+    const int32_t prev = __shfl_up(c, 1, 64);
+    const bool head = live && (lane == 0 || prev != c);
+    const unsigned long long heads = __ballot(head);
+    const int nlive = __popcll(__ballot(live));  // live lanes are a prefix
+    // first lane of this lane's run, and the run's end
+    const unsigned long long below = heads & ((2ull << lane) - 1ull);
+    const int first = below ? 63 - __clzll(below) : lane;
+    const unsigned long long above = heads & ~((2ull << lane) - 1ull);
+    int next = above ? __ffsll((long long)above) - 1 : 64;
+    if (next > nlive) next = nlive;
+    int32_t base = 0;
+    if (head) base = atomicAdd(&counts[c], next - lane);
+    base = __shfl(base, first, 64);
+    if (!live) return;
     cell[p] = c;
-    slot[p] = atomicAdd(&counts[c], 1);
+    slot[p] = base + (lane - first);
 }
 
 // Inclusive scan over the 64 lanes of a wavefront.

@@ -62,6 +62,8 @@ struct srm_ctx {
     Counters *dcnt = nullptr;
     Counters *hcnt = nullptr;  // pinned
     double *dtmp = nullptr;    // 3n doubles: id-order staging
+    int32_t *rowcnt = nullptr; // srm_pairs: partners per id, then row offsets
+    int32_t *rowoff = nullptr;
     int32_t *itmp = nullptr;   // n ints
     int32_t *ovf = nullptr;    // tiled migration: 8 overflow counts + 8 tile lists
     int32_t *failed = nullptr; // [0] count, then slots with accept code 0
@@ -603,19 +605,131 @@ srm_status srm_last_acc(srm_ctx *c, uint8_t *acc_by_id)
     return SRM_OK;
 }
 
+namespace {
+
+// Device staging for the diagnostics: copy host inputs in, run, copy out.
+struct DevArena {
+    void *p[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~DevArena()
+    {
+        for (void *q : p)
+            if (q) (void)hipFree(q);
+    }
+};
+
+}  // namespace
+
+namespace {
+
+// Grid for a static neighbour search with cutoff `reach`: cells at least
+// `reach` wide, N_a >= 4 or a single cell per axis, capped like the sweep grid.
+Grid cutoff_grid(const srm_ctx *c, double reach)
+{
+    Grid g{};
+    for (int a = 0; a < 3; ++a) {
+        g.box[a] = c->p.box[a];
+        g.half[a] = 0.5 * c->p.box[a];
+        if (a >= c->dim) {
+            g.na[a] = 1;
+            g.inv_w[a] = 1.0 / c->p.box[a];
+            continue;
+        }
+        int64_t m;
+        const double q = (reach > 0.0) ? c->p.box[a] / reach : 0.0;
+        if (!(reach > 0.0) || q >= (double)c->ncap) m = c->ncap;
+        else m = (int64_t)q;
+        g.na[a] = (int32_t)((m >= 4) ? m : 1);
+        g.inv_w[a] = (double)g.na[a] / c->p.box[a];
+    }
+    g.ncell = g.na[0] * g.na[1] * g.na[2];
+    return g;
+}
+
+// Per-id row counts and offsets for srm_pairs (allocated on first use).
+srm_status ensure_rows(srm_ctx *c)
+{
+    if (c->rowcnt) return SRM_OK;
+    hipError_t e;
+    if ((e = c->alloc(&c->rowcnt, (size_t)c->n + 2)) || (e = c->alloc(&c->rowoff, (size_t)c->n + 2)))
+        return fail(SRM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    return SRM_OK;
+}
+
+}  // namespace
+
 srm_status srm_pairs(srm_ctx *c, double gap, int64_t cap, int32_t *ij, int64_t *count,
                      int32_t mem_kind)
 {
-    (void)gap; (void)cap; (void)ij; (void)mem_kind;
     if (!c || !count) return fail(SRM_EINVAL, "NULL argument");
-    return fail(SRM_EINVAL, "srm_pairs: not built yet");
+    if (!(gap >= 0.0) || !isfinite(gap)) return fail(SRM_EINVAL, "gap must be finite and >= 0");
+    if (mem_kind != SRM_MEM_HOST && mem_kind != SRM_MEM_DEVICE)
+        return fail(SRM_EINVAL, "bad mem_kind");
+    if (cap < 0 || (cap > 0 && !ij)) return fail(SRM_EINVAL, "bad output buffer");
+    srm_status st = ensure_rows(c);
+    if (st) return st;
+    const double reach = 2.0 * (c->s * c->rho_max) + gap;
+    const Grid g = cutoff_grid(c, reach);
+    if ((st = bin(c, c->P, c->T, g))) return st;
+    HIP_TRY(pairs_count(c->dim, c->T, c->sc.start, g, c->n, c->p.shape, c->s, gap, c->rowcnt,
+                        c->stream));
+    HIP_TRY(scan_counts(c->rowcnt, c->rowoff, c->sc.partials, c->n, c->stream));
+    int32_t total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, c->rowoff + c->n, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *count = total;
+    if (total > cap) return fail(SRM_ECAPACITY, "%d pairs exceed capacity %lld", total, (long long)cap);
+    if (total == 0) return SRM_OK;
+    DevArena d;
+    HIP_TRY(hipMalloc(&d.p[0], (size_t)total * sizeof(int32_t)));
+    int32_t *out = ij;
+    if (mem_kind == SRM_MEM_HOST) {
+        HIP_TRY(hipMalloc(&d.p[1], (size_t)total * 2 * sizeof(int32_t)));
+        out = (int32_t *)d.p[1];
+    }
+    HIP_TRY(pairs_emit(c->dim, c->T, c->sc.start, g, c->n, c->p.shape, c->s, gap, c->rowoff,
+                       (int32_t *)d.p[0], out, c->stream));
+    if (mem_kind == SRM_MEM_HOST)
+        HIP_TRY(hipMemcpyAsync(ij, out, (size_t)total * 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                               c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SRM_OK;
 }
 
-srm_status srm_rdf(srm_ctx *c, int32_t nbins, double r_max, uint64_t *counts, double *g)
+srm_status srm_rdf(srm_ctx *c, int32_t nbins, double r_max, uint64_t *counts, double *g_out)
 {
-    (void)nbins; (void)r_max; (void)counts; (void)g;
-    if (!c) return fail(SRM_EINVAL, "ctx is NULL");
-    return fail(SRM_EINVAL, "srm_rdf: not built yet");
+    if (!c || !counts) return fail(SRM_EINVAL, "NULL argument");
+    if (nbins < 1 || nbins > 65536) return fail(SRM_EINVAL, "nbins out of range");
+    double lmin = c->p.box[0];
+    for (int a = 1; a < c->dim; ++a) lmin = c->p.box[a] < lmin ? c->p.box[a] : lmin;
+    if (!(r_max > 0.0) || !(r_max <= 0.5 * lmin)) return fail(SRM_EINVAL, "need 0 < r_max <= L/2");
+    const Grid g = cutoff_grid(c, r_max);
+    srm_status st;
+    if ((st = bin(c, c->P, c->T, g))) return st;
+    DevArena d;
+    HIP_TRY(hipMalloc(&d.p[0], (size_t)nbins * sizeof(uint64_t)));
+    HIP_TRY(launch_fill_i32((int32_t *)d.p[0], 2 * (int64_t)nbins, 0, c->stream));
+    const double inv = (double)nbins / r_max;
+    HIP_TRY(rdf_counts(c->dim, c->T, c->sc.start, g, c->n, nbins, inv,
+                       (unsigned long long *)d.p[0], c->stream));
+    HIP_TRY(hipMemcpyAsync(counts, d.p[0], (size_t)nbins * sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (g_out) {
+        double vbox = 1.0;
+        for (int a = 0; a < c->dim; ++a) vbox *= c->p.box[a];
+        const double coeff = (c->dim == 2) ? M_PI : 4.0 * M_PI / 3.0;
+        const double npairs = 0.5 * (double)c->n * (double)(c->n - 1);
+        const double dr = r_max / nbins;
+        for (int32_t b = 0; b < nbins; ++b) {
+            const double r0 = b * dr, r1 = (b + 1) * dr;
+            const double shell = (c->dim == 2) ? coeff * (r1 * r1 - r0 * r0)
+                                               : coeff * (r1 * r1 * r1 - r0 * r0 * r0);
+            const double ideal = npairs * shell / vbox;
+            g_out[b] = ideal > 0.0 ? (double)counts[b] / ideal : 0.0;
+        }
+    }
+    return SRM_OK;
 }
 
 srm_status srm_profile_enable(srm_ctx *c, int32_t on)
@@ -637,19 +751,6 @@ srm_status srm_profile_read(srm_ctx *c, srm_profile *out)
     return SRM_OK;
 }
 
-namespace {
-
-// Device staging for the diagnostics: copy host inputs in, run, copy out.
-struct DevArena {
-    void *p[4] = {nullptr, nullptr, nullptr, nullptr};
-    ~DevArena()
-    {
-        for (void *q : p)
-            if (q) (void)hipFree(q);
-    }
-};
-
-}  // namespace
 
 srm_status srm_debug_fp(const double *a, const double *b, int64_t n, double *sqrt_out,
                         double *div_out)

@@ -175,4 +175,61 @@ __device__ __forceinline__ bool disks_intersect(double dx, double dy, double dz,
     return D * D <= (4.0 * Ap) * Bp;
 }
 
+// Slices of a cell-sorted array covering the 3^dim cells around a cell.
+template <int DIM>
+struct Rows {
+    static constexpr int kRows = (DIM == 3) ? 9 : 3;
+    static constexpr int kRanges = 2 * kRows;  // a row of 3 cells is <= 2 slices
+};
+
+__device__ __forceinline__ int32_t wrap_index(int32_t c, int32_t n)
+{
+    c += (c < 0) ? n : 0;
+    c -= (c >= n) ? n : 0;
+    return c;
+}
+
+// Slices of the cell-sorted arrays covering the 3^dim cells around
+// (cx, cy, cz).  Cells (cx-1, cx, cx+1) of one row are consecutive in the
+// linear order unless the row wraps, so a row is one slice, or two at the
+// x boundary.  Axes with a single cell contribute only offset 0.
+template <int DIM>
+__device__ __forceinline__ void stencil_slices(const Grid &g, const int32_t *__restrict__ start,
+                                               int32_t cx, int32_t cy, int32_t cz, int32_t *lo,
+                                               int32_t *hi)
+{
+    const int32_t na0 = g.na[0], na1 = g.na[1], na2 = g.na[2];
+#pragma unroll
+    for (int iz = 0; iz < (DIM == 3 ? 3 : 1); ++iz) {
+#pragma unroll
+        for (int iy = 0; iy < 3; ++iy) {
+            const int r = (iz * 3 + iy) * 2;
+            lo[r] = hi[r] = lo[r + 1] = hi[r + 1] = 0;
+            const int32_t dy = iy - 1, dz = (DIM == 3) ? iz - 1 : 0;
+            if (na1 < 4 && dy != 0) continue;
+            if (DIM == 3 && na2 < 4 && dz != 0) continue;
+            const int32_t yy = wrap_index(cy + dy, na1);
+            const int32_t zz = (DIM == 3) ? wrap_index(cz + dz, na2) : 0;
+            const int32_t row = na0 * (yy + na1 * zz);
+            if (na0 < 4) {
+                lo[r] = start[row];
+                hi[r] = start[row + 1];
+            } else if (cx >= 1 && cx <= na0 - 2) {
+                lo[r] = start[row + cx - 1];
+                hi[r] = start[row + cx + 2];
+            } else if (cx == 0) {
+                lo[r] = start[row];
+                hi[r] = start[row + 2];
+                lo[r + 1] = start[row + na0 - 1];
+                hi[r + 1] = start[row + na0];
+            } else {
+                lo[r] = start[row + na0 - 2];
+                hi[r] = start[row + na0];
+                lo[r + 1] = start[row];
+                hi[r + 1] = start[row + 1];
+            }
+        }
+    }
+}
+
 }  // namespace srm

@@ -90,6 +90,16 @@ hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int 
 hipError_t check_overlaps(int dim, int shape, bool poly, const PassArgs &a, bool check_all,
                           Counters *cnt, hipStream_t stream);
 
+// Pair enumeration and distance histogram of a binned configuration
+// (k_pairs.hip).  rowcnt/rowoff are indexed by particle id.
+hipError_t pairs_count(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
+                       int shape, double s, double gap, int32_t *rowcnt, hipStream_t stream);
+hipError_t pairs_emit(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
+                      int shape, double s, double gap, const int32_t *rowoff, int32_t *partner,
+                      int32_t *ij, hipStream_t stream);
+hipError_t rdf_counts(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
+                      int32_t nbins, double inv, unsigned long long *counts, hipStream_t stream);
+
 // Diagnostics of the device arithmetic (k_diag.hip).
 hipError_t diag_fp(const double *a, const double *b, int32_t n, double *sq, double *dv,
                    hipStream_t s);

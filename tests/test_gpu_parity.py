@@ -304,3 +304,62 @@ def test_full_run_fraction_and_no_overlap(srm, oracle_lib):
     o = oracle_lib.Oracle.from_workload(w, pos=pos, s0=s, sweep0=t)
     assert not o.overlap()
     g.close()
+
+
+# ------------------------------------------------------- pairs and distances
+
+@pytest.mark.parametrize("dim,n,poly", [(2, 3000, False), (3, 12000, False), (3, 4000, True)])
+def test_pairs_match_oracle(srm, oracle_lib, dim, n, poly):
+    w = _mk(dim, n, 120 + n % 13, 0.35, polydisperse_sigma=0.2 if poly else None)
+    o = oracle_lib.Oracle.from_workload(w)
+    o.run(3000)
+    g = _gpu_from_oracle(srm, o, w)
+    for gap in (0.0, 0.2 * o.s, 1.5 * o.s):
+        ref = o.pairs_brute(gap)
+        got = g.pairs(gap)
+        _say(f"pairs dim={dim} n={n} gap={gap:.3g}: {len(ref)}")
+        assert np.array_equal(got.astype(np.int64), ref.astype(np.int64))
+    g.close()
+
+
+def test_pairs_capacity_error(srm):
+    w = _mk(3, 3000, 125, 0.3)
+    g = srm.SRM.from_workload(w)
+    import ctypes as C
+    cnt = C.c_int64()
+    buf = np.zeros(2 * 4, dtype=np.int32)
+    st = srm.lib().srm_pairs(g._ctx, 0.05, 4, C.c_void_p(buf.ctypes.data), C.byref(cnt), 0)
+    assert st == srm.ECAPACITY and cnt.value > 4 and not buf.any()
+    assert len(g.pairs(0.05)) == cnt.value
+    g.close()
+
+
+def test_platelet_pairs_match_oracle(srm, oracle_lib):
+    w = srm_inputs.make("platelets", n=2500, seed=7, f_target=0.02)
+    o = oracle_lib.Oracle.from_workload(w)
+    for _ in range(30):
+        o.sweep()
+    g = _gpu_from_oracle(srm, o, w)
+    for gap in (0.0, 0.3 * o.s, 1.0 * o.s):
+        assert np.array_equal(g.pairs(gap).astype(np.int64), o.pairs_brute(gap).astype(np.int64))
+    g.close()
+
+
+@pytest.mark.parametrize("dim,n,nbins", [(2, 3000, 64), (3, 12000, 64), (3, 5000, 10000)])
+def test_rdf_counts_match_oracle(srm, oracle_lib, dim, n, nbins):
+    w = _mk(dim, n, 130 + n % 7, 0.3)
+    o = oracle_lib.Oracle.from_workload(w)
+    o.run(3000)
+    g = _gpu_from_oracle(srm, o, w)
+    r_max = 5.0 * o.s
+    counts, gr = g.rdf(nbins, r_max)
+    ref = o.rdf_brute(nbins, r_max)
+    assert np.array_equal(counts, ref)
+    # normalisation: an ideal-gas shell count
+    dr = r_max / nbins
+    r0 = np.arange(nbins) * dr
+    r1 = r0 + dr
+    shell = (math.pi * (r1**2 - r0**2)) if dim == 2 else (4 * math.pi / 3 * (r1**3 - r0**3))
+    ideal = 0.5 * n * (n - 1) * shell
+    assert np.allclose(gr, counts / ideal, rtol=1e-12)
+    g.close()
