@@ -141,6 +141,14 @@ srm_status srm_rdf(srm_ctx *ctx, int32_t nbins, double r_max, uint64_t *counts, 
 srm_status srm_get_state(srm_ctx *ctx, double *pos, double *normals, double *s,
                          int64_t *sweep, int32_t mem_kind);
 
+/* Replace the committed positions (and normals, or NULL) with pos (dim*n
+ * SoA, id order, every coordinate in [0, L_a)); s and the sweep counter are
+ * kept.  Overlaps are allowed: the next srm_sweep resolves them when it
+ * commits (with c_w = 0 it only migrates), and reports a shake otherwise.
+ * Used after an external update of the positions, e.g. a gradient step. */
+srm_status srm_set_state(srm_ctx *ctx, const double *pos, const double *normals,
+                         int32_t mem_kind);
+
 /* Release the context and all of its device memory.  NULL is a no-op. */
 srm_status srm_free(srm_ctx *ctx);
 
@@ -166,6 +174,43 @@ srm_status srm_pass(srm_ctx *ctx, double grid_s, double radius_s, int32_t kind, 
 
 /* Accept codes of the last pass run by srm_sweep or srm_pass, id order. */
 srm_status srm_last_acc(srm_ctx *ctx, uint8_t *acc_by_id);
+
+/* ---- differentiable descriptor: soft g(r) + overlap energy -------------- */
+
+/* A workspace for configurations of n particles in a fixed periodic box.
+ * Descriptor (steering clustered configurations toward a target radial
+ * distribution; SRM's exact test stays the judge of admissibility):
+ *   g_b = norm_b * sum_{i<j} K_b(r_ij) w(r_ij),  b < nbins,
+ *   K_b(r) = exp(-(r - c_b)^2 / (2 h^2)) / (h sqrt(2 pi)),
+ *   c_b = (b + 1/2) D, h = D = r_c / nbins,
+ *   w(r) = C2 taper, 1 below r_c, 0 above r_c + 4h,
+ *   norm_b = V / (n(n-1)/2 * 4 pi c_b^2)   (2D: 2 pi c_b),
+ *   E = kappa/2 * sum_{i<j} max(0, R_i + R_j - r_ij)^2,
+ * r_ij the minimum-image distance; FP64 throughout.  Pairs are searched up
+ * to r_c + 4h, which must cover every overlapping pair (2 R_max <= r_c +
+ * 4h).  Every buffer below is device memory; all work runs on `stream`;
+ * results are deterministic (fixed-order reductions, no atomics). */
+typedef struct {
+    int32_t dim;      /* 2 or 3 */
+    int32_t nbins;    /* 1 .. 64 */
+    double box[3];    /* periodic box edges */
+    double r_c;       /* bins cover [0, r_c] */
+    double kappa;     /* penalty stiffness */
+} srm_softrdf_params;
+
+typedef struct srm_soft srm_soft;
+
+srm_status srm_softrdf_create(const srm_softrdf_params *p, int64_t n, void *stream,
+                              srm_soft **out);
+/* pos: dim*n SoA in [0, L_a); radii: n.  g_out: nbins; energy: 1 double. */
+srm_status srm_softrdf_forward(srm_soft *ctx, const double *pos, const double *radii,
+                               double *g_out, double *energy);
+/* dg: dL/dg (nbins); dE: dL/dE (1 double).  grad_pos: dim*n SoA;
+ * grad_radii: n.  Pairs are recomputed from pos, not stored. */
+srm_status srm_softrdf_backward(srm_soft *ctx, const double *pos, const double *radii,
+                                const double *dg, const double *dE, double *grad_pos,
+                                double *grad_radii);
+srm_status srm_softrdf_free(srm_soft *ctx);
 
 /* ---- device-time profile ------------------------------------------------ */
 

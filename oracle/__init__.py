@@ -53,6 +53,11 @@ class State(C.Structure):
                 ("rho", C.POINTER(C.c_double)), ("s", C.c_double), ("t", C.c_int64)]
 
 
+class SoftParams(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nbins", C.c_int32), ("box", C.c_double * 3),
+                ("r_c", C.c_double), ("kappa", C.c_double)]
+
+
 class SweepInfo(C.Structure):
     _fields_ = [("committed", C.c_int32), ("passes_main", C.c_int32),
                 ("passes_shake", C.c_int32), ("pad", C.c_int32), ("na", C.c_int64 * 3),
@@ -93,6 +98,9 @@ def lib():
         L.o_rdf_brute.argtypes = [C.POINTER(State), C.c_int32, C.c_double,
                                   C.POINTER(C.c_uint64)]
         L.o_disks_intersect.argtypes = [dp, dp, C.c_double, dp, dp, C.c_double, dp]
+        L.o_softrdf_fwd.argtypes = [C.POINTER(SoftParams), C.c_int64, dp, dp, dp, dp]
+        L.o_softrdf_grad.argtypes = [C.POINTER(SoftParams), C.c_int64, dp, dp, dp, C.c_double,
+                                     dp, dp]
         L.o_disks_intersect.restype = C.c_int
         for f in ("o_pass", "o_overlap", "o_sweep", "o_run", "o_rdf_brute", "o_bin"):
             getattr(L, f).restype = C.c_int
@@ -125,6 +133,42 @@ def disks_intersect(c1, n1, a1, c2, n2, a2, box=(1.0, 1.0, 1.0)) -> bool:
     arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (c1, n1, c2, n2, box)]
     return bool(lib().o_disks_intersect(_dp(arrs[0]), _dp(arrs[1]), float(a1), _dp(arrs[2]),
                                         _dp(arrs[3]), float(a2), _dp(arrs[4])))
+
+
+def _soft_params(dim, nbins, r_c, box=(1.0, 1.0, 1.0), kappa=1.0):
+    sp = SoftParams()
+    sp.dim, sp.nbins, sp.r_c, sp.kappa = int(dim), int(nbins), float(r_c), float(kappa)
+    box3 = list(box) + [1.0] * (3 - len(box))
+    for a in range(3):
+        sp.box[a] = float(box3[a])
+    return sp
+
+
+def softrdf_forward(pos, radii, *, dim, nbins, r_c, box=(1.0, 1.0, 1.0), kappa=1.0):
+    """Soft g(r) (nbins) and overlap energy of a configuration; pos is SoA
+    (dim, n), radii (n,).  All pairs, FP64."""
+    n = np.asarray(radii).shape[0]
+    rows = _rows(pos, n)
+    r = np.ascontiguousarray(radii, dtype=np.float64)
+    g = np.zeros(nbins)
+    e = np.zeros(1)
+    sp = _soft_params(dim, nbins, r_c, box, kappa)
+    lib().o_softrdf_fwd(C.byref(sp), n, _dp(rows), _dp(r), _dp(g), _dp(e))
+    return g, float(e[0])
+
+
+def softrdf_gradient(pos, radii, dg, dE, *, dim, nbins, r_c, box=(1.0, 1.0, 1.0), kappa=1.0):
+    """Gradient (SoA (dim, n), (n,)) of sum_b dg_b g_b + dE * E."""
+    n = np.asarray(radii).shape[0]
+    rows = _rows(pos, n)
+    r = np.ascontiguousarray(radii, dtype=np.float64)
+    dgv = np.ascontiguousarray(dg, dtype=np.float64)
+    gp = np.zeros((n, 3))
+    gr = np.zeros(n)
+    sp = _soft_params(dim, nbins, r_c, box, kappa)
+    lib().o_softrdf_grad(C.byref(sp), n, _dp(rows), _dp(r), _dp(dgv), float(dE), _dp(gp),
+                         _dp(gr))
+    return np.ascontiguousarray(gp[:, :dim].T), gr
 
 
 class Oracle:

@@ -45,6 +45,10 @@
  *    rejected together.
  */
 #include <math.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -634,4 +638,125 @@ int o_rdf_brute(const o_state *st, int32_t nbins, double r_max, uint64_t *counts
             }
         }
     return O_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Soft-binned radial distribution and overlap penalty (differentiable  */
+/* steering of configurations toward a target g(r)).                   */
+/*                                                                      */
+/* Bins b = 0..nb-1 of width D = r_c / nb, centres c_b = (b + 1/2) D,   */
+/* Gaussian kernel K_b(r) = exp(-(r - c_b)^2 / (2 h^2)) / (h sqrt(2 pi)) */
+/* with h = D, and a C2 taper w(r) = 1 - 10t^3 + 15t^4 - 6t^5,          */
+/* t = (r - r_c) / (4h) on [r_c, r_c + 4h] (1 before, 0 after).          */
+/*   g_b = norm_b * sum_{i<j} K_b(r_ij) w(r_ij),                         */
+/*   norm_b = V / (N(N-1)/2 * 4 pi c_b^2)   (3D; 2D: 2 pi c_b),          */
+/*   E = kappa/2 * sum_{i<j} max(0, R_i + R_j - r_ij)^2,                 */
+/* with r_ij the minimum-image distance.  All pairs, all in FP64.        */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t dim, nbins;
+    double box[3];
+    double r_c;
+    double kappa;
+} o_softrdf_params;
+
+static double o_taper(double r, double r_c, double h, double *dw)
+{
+    double span = 4.0 * h;
+    if (r <= r_c) { *dw = 0.0; return 1.0; }
+    if (r >= r_c + span) { *dw = 0.0; return 0.0; }
+    double t = (r - r_c) / span;
+    double t2 = t * t, t3 = t2 * t;
+    *dw = (-30.0 * t2 + 60.0 * t3 - 30.0 * t2 * t2) / span;
+    return 1.0 - 10.0 * t3 + 15.0 * t3 * t - 6.0 * t3 * t2;
+}
+
+static double o_soft_norm(const o_softrdf_params *p, int64_t n, int b)
+{
+    double D = p->r_c / p->nbins;
+    double c = (b + 0.5) * D;
+    double vol = 1.0;
+    for (int a = 0; a < p->dim; ++a) vol *= p->box[a];
+    double pairs = 0.5 * (double)n * (double)(n - 1);
+    double shell = (p->dim == 3) ? 4.0 * M_PI * c * c : 2.0 * M_PI * c;
+    return vol / (pairs * shell);
+}
+
+static void o_pair_vec(const o_softrdf_params *p, const double *xi, const double *xj, double d[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        if (a >= p->dim) { d[a] = 0.0; continue; }
+        d[a] = o_minimg(xi[a] - xj[a], p->box[a]);
+    }
+}
+
+void o_softrdf_fwd(const o_softrdf_params *p, int64_t n, const double *pos, const double *radii,
+                   double *g, double *energy)
+{
+    double D = p->r_c / p->nbins, h = D;
+    double cut = p->r_c + 4.0 * h;
+    double c0 = 1.0 / (h * sqrt(2.0 * M_PI));
+    for (int b = 0; b < p->nbins; ++b) g[b] = 0.0;
+    double E = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = i + 1; j < n; ++j) {
+            double d[3];
+            o_pair_vec(p, &pos[3 * i], &pos[3 * j], d);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            double ov = radii[i] + radii[j] - r;
+            if (ov > 0.0) E += ov * ov;
+            if (r >= cut) continue;
+            double dw;
+            double w = o_taper(r, p->r_c, h, &dw);
+            for (int b = 0; b < p->nbins; ++b) {
+                double u = (r - (b + 0.5) * D) / h;
+                g[b] += c0 * exp(-0.5 * u * u) * w;
+            }
+        }
+    }
+    for (int b = 0; b < p->nbins; ++b) g[b] *= o_soft_norm(p, n, b);
+    *energy = 0.5 * p->kappa * E;
+}
+
+/* Gradient of L with dL/dg_b = dg[b] and dL/dE = dE with respect to every
+ * position (n rows of 3) and radius. */
+void o_softrdf_grad(const o_softrdf_params *p, int64_t n, const double *pos, const double *radii,
+                    const double *dg, double dE, double *gpos, double *grad_r)
+{
+    double D = p->r_c / p->nbins, h = D;
+    double cut = p->r_c + 4.0 * h;
+    double c0 = 1.0 / (h * sqrt(2.0 * M_PI));
+    for (int64_t i = 0; i < 3 * n; ++i) gpos[i] = 0.0;
+    for (int64_t i = 0; i < n; ++i) grad_r[i] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = i + 1; j < n; ++j) {
+            double d[3];
+            o_pair_vec(p, &pos[3 * i], &pos[3 * j], d);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (r == 0.0) continue;
+            /* dL/dr for this pair */
+            double dLdr = 0.0;
+            double ov = radii[i] + radii[j] - r;
+            if (ov > 0.0) {
+                dLdr += dE * p->kappa * (-ov);
+                grad_r[i] += dE * p->kappa * ov;
+                grad_r[j] += dE * p->kappa * ov;
+            }
+            if (r < cut) {
+                double dw;
+                double w = o_taper(r, p->r_c, h, &dw);
+                for (int b = 0; b < p->nbins; ++b) {
+                    double u = (r - (b + 0.5) * D) / h;
+                    double k = c0 * exp(-0.5 * u * u);
+                    double dk = k * (-u / h);
+                    dLdr += dg[b] * o_soft_norm(p, n, b) * (dk * w + k * dw);
+                }
+            }
+            for (int a = 0; a < p->dim; ++a) {
+                double ua = d[a] / r;
+                gpos[3 * i + a] += dLdr * ua;
+                gpos[3 * j + a] -= dLdr * ua;
+            }
+        }
+    }
 }

@@ -26,7 +26,9 @@ OK, EINVAL, ENOMEM, EDEVICE, EOVERLAP, ENOTCONV, ECAPACITY = 0, -1, -2, -3, -4, 
 
 SYMBOLS = ["srm_init", "srm_sweep", "srm_run_to_fraction", "srm_pairs", "srm_rdf",
            "srm_get_state", "srm_free", "srm_last_error", "srm_grid", "srm_cells", "srm_pass",
-           "srm_last_acc", "srm_profile_enable", "srm_profile_read", "srm_debug_fp",
+           "srm_last_acc", "srm_set_state", "srm_softrdf_create", "srm_softrdf_forward",
+           "srm_softrdf_backward", "srm_softrdf_free", "srm_profile_enable", "srm_profile_read",
+           "srm_debug_fp",
            "srm_debug_philox", "srm_debug_unitvec"]
 
 

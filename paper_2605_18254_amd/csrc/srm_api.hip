@@ -558,6 +558,42 @@ srm_status srm_get_state(srm_ctx *c, double *pos, double *normals, double *s, in
     return SRM_OK;
 }
 
+srm_status srm_set_state(srm_ctx *c, const double *pos, const double *normals,
+                         int32_t mem_kind)
+{
+    if (!c || !pos) return fail(SRM_EINVAL, "NULL argument");
+    if (mem_kind != SRM_MEM_HOST && mem_kind != SRM_MEM_DEVICE)
+        return fail(SRM_EINVAL, "bad mem_kind");
+    if (c->plate != (normals != nullptr)) return fail(SRM_EINVAL, "normals iff platelets");
+    const size_t n = (size_t)c->n;
+    const hipMemcpyKind kind = (mem_kind == SRM_MEM_HOST) ? hipMemcpyHostToDevice
+                                                          : hipMemcpyDeviceToDevice;
+    // T <- input in id order (rho copied from P in id order first)
+    if (c->poly) {
+        const double *r[1] = {c->P.rho};
+        HIP_TRY(to_id_order(r, 1, c->P.id, c->n, c->dtmp, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->T.rho, c->dtmp, n * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
+    }
+    for (int a = 0; a < c->dim; ++a)
+        HIP_TRY(hipMemcpyAsync(c->T.x[a], pos + a * n, n * sizeof(double), kind, c->stream));
+    if (normals)
+        for (int a = 0; a < 3; ++a)
+            HIP_TRY(hipMemcpyAsync(c->T.nrm[a], normals + a * n, n * sizeof(double), kind,
+                                   c->stream));
+    HIP_TRY(launch_iota(c->T.id, c->n, c->stream));
+    const Grid g = make_grid(c, c->s * c->rho_max);
+    HIP_TRY(launch_zero_counters(c->dcnt, c->stream));
+    srm_status st = bin(c, c->T, c->Q, g);
+    if (st) return st;
+    HIP_TRY(hipMemcpyAsync(c->hcnt, c->dcnt, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->hcnt->bad) return fail(SRM_EINVAL, "a coordinate is outside [0, L) or NaN");
+    std::swap(c->P, c->Q);
+    c->acc_valid = false;
+    return SRM_OK;
+}
+
 srm_status srm_grid(srm_ctx *c, double s, int32_t na[3])
 {
     if (!c || !na) return fail(SRM_EINVAL, "NULL argument");
@@ -797,6 +833,148 @@ srm_status srm_debug_unitvec(int32_t dim, uint64_t seed, uint32_t t, uint32_t wo
     HIP_TRY(hipMalloc(&d.p[0], (size_t)n * 24));
     HIP_TRY(diag_unitvec(dim, seed, t, word, stream, len, (int32_t)n, (double *)d.p[0], nullptr));
     HIP_TRY(hipMemcpy(out, d.p[0], (size_t)n * 24, hipMemcpyDeviceToHost));
+    return SRM_OK;
+}
+
+// ---------------------------------------------------------------- soft g(r)
+
+}  // extern "C"
+
+struct srm_soft {
+    srm_softrdf_params p{};
+    int32_t n = 0;
+    hipStream_t stream = nullptr;
+    int64_t ncap = 0;
+    PBuf in{}, sorted{};
+    Scratch sc{};
+    Counters *dcnt = nullptr;
+    double *partial = nullptr;
+    Grid g{};
+    std::vector<void *> allocs;
+    template <class T_>
+    hipError_t alloc(T_ **ptr, size_t count)
+    {
+        void *v = nullptr;
+        hipError_t e = hipMalloc(&v, (count > 0 ? count : 1) * sizeof(T_));
+        if (e == hipSuccess) {
+            allocs.push_back(v);
+            *ptr = (T_ *)v;
+        }
+        return e;
+    }
+    ~srm_soft()
+    {
+        for (void *v : allocs) (void)hipFree(v);
+    }
+};
+
+namespace {
+
+srm_status soft_bin(srm_soft *c, const double *pos, const double *radii)
+{
+    const size_t n = (size_t)c->n;
+    for (int a = 0; a < c->p.dim; ++a)
+        HIP_TRY(hipMemcpyAsync(c->in.x[a], pos + a * n, n * sizeof(double),
+                               hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->in.rho, radii, n * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+    HIP_TRY(launch_iota(c->in.id, c->n, c->stream));
+    HIP_TRY(bin_particles(c->p.dim, c->in, c->sorted, c->n, c->g, c->sc, c->dcnt, c->stream));
+    return SRM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+srm_status srm_softrdf_create(const srm_softrdf_params *p, int64_t n, void *stream,
+                              srm_soft **out)
+{
+    if (!p || !out) return fail(SRM_EINVAL, "NULL argument");
+    if (p->dim != 2 && p->dim != 3) return fail(SRM_EINVAL, "dim must be 2 or 3");
+    if (p->nbins < 1 || p->nbins > 64) return fail(SRM_EINVAL, "nbins must be 1..64");
+    if (n < 2 || n > 0x7fffffffLL) return fail(SRM_EINVAL, "n out of range");
+    if (!(p->r_c > 0.0) || !isfinite(p->r_c) || !(p->kappa >= 0.0))
+        return fail(SRM_EINVAL, "bad r_c or kappa");
+    for (int a = 0; a < p->dim; ++a)
+        if (!(p->box[a] > 0.0)) return fail(SRM_EINVAL, "box edge <= 0");
+    srm_soft *c = new (std::nothrow) srm_soft();
+    if (!c) return fail(SRM_ENOMEM, "host allocation failed");
+    c->p = *p;
+    if (c->p.dim == 2) c->p.box[2] = 1.0;
+    c->n = (int32_t)n;
+    c->stream = (hipStream_t)stream;
+    c->ncap = cell_cap(c->p.dim, n);
+    // neighbour grid: cells at least r_c + 4h wide
+    const double cut = p->r_c + 4.0 * (p->r_c / p->nbins);
+    Grid &g = c->g;
+    for (int a = 0; a < 3; ++a) {
+        g.box[a] = c->p.box[a];
+        g.half[a] = 0.5 * c->p.box[a];
+        if (a >= c->p.dim) {
+            g.na[a] = 1;
+            g.inv_w[a] = 1.0 / c->p.box[a];
+            continue;
+        }
+        const double q = c->p.box[a] / cut;
+        const int64_t m = (q >= (double)c->ncap) ? c->ncap : (int64_t)q;
+        g.na[a] = (int32_t)(m >= 4 ? m : 1);
+        g.inv_w[a] = (double)g.na[a] / c->p.box[a];
+    }
+    g.ncell = g.na[0] * g.na[1] * g.na[2];
+    hipError_t e = hipSuccess;
+    for (int a = 0; a < c->p.dim && !e; ++a)
+        if ((e = c->alloc(&c->in.x[a], n)) == hipSuccess) e = c->alloc(&c->sorted.x[a], n);
+    if (!e) e = c->alloc(&c->in.id, n);
+    if (!e) e = c->alloc(&c->sorted.id, n);
+    if (!e) e = c->alloc(&c->in.rho, n);
+    if (!e) e = c->alloc(&c->sorted.rho, n);
+    c->sc.cap = n + 2;
+    if (!e) e = c->alloc(&c->sc.cell, n);
+    if (!e) e = c->alloc(&c->sc.slot, n);
+    if (!e) e = c->alloc(&c->sc.counts, (size_t)c->sc.cap);
+    if (!e) e = c->alloc(&c->sc.start, (size_t)c->sc.cap + 1);
+    if (!e) e = c->alloc(&c->sc.partials, (size_t)(c->sc.cap / 2048 + 2));
+    if (!e) e = c->alloc(&c->dcnt, 1);
+    if (!e) e = c->alloc(&c->partial, (size_t)soft_blocks(c->n) * soft_partial_stride());
+    if (e) {
+        delete c;
+        return fail(SRM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return SRM_OK;
+}
+
+srm_status srm_softrdf_forward(srm_soft *c, const double *pos, const double *radii,
+                               double *g_out, double *energy)
+{
+    if (!c || !pos || !radii || !g_out || !energy) return fail(SRM_EINVAL, "NULL argument");
+    srm_status st = soft_bin(c, pos, radii);
+    if (st) return st;
+    HIP_TRY(soft_forward(c->p.dim, c->sorted, c->sc.start, c->g, c->n, c->p.nbins, c->p.r_c,
+                         c->p.kappa, c->partial, g_out, energy, c->stream));
+    return SRM_OK;
+}
+
+srm_status srm_softrdf_backward(srm_soft *c, const double *pos, const double *radii,
+                                const double *dg, const double *dE, double *grad_pos,
+                                double *grad_radii)
+{
+    if (!c || !pos || !radii || !dg || !dE || !grad_pos || !grad_radii)
+        return fail(SRM_EINVAL, "NULL argument");
+    srm_status st = soft_bin(c, pos, radii);
+    if (st) return st;
+    HIP_TRY(soft_backward(c->p.dim, c->sorted, c->sc.start, c->g, c->n, c->p.nbins, c->p.r_c,
+                          c->p.kappa, dg, dE, grad_pos, grad_radii, c->stream));
+    return SRM_OK;
+}
+
+srm_status srm_softrdf_free(srm_soft *c)
+{
+    if (!c) return SRM_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    delete c;
     return SRM_OK;
 }
 

@@ -100,6 +100,16 @@ hipError_t pairs_emit(int dim, const PBuf &b, const int32_t *start, const Grid &
 hipError_t rdf_counts(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
                       int32_t nbins, double inv, unsigned long long *counts, hipStream_t stream);
 
+// Soft-binned g(r) + overlap energy and its gradient (k_softrdf.hip).
+int32_t soft_blocks(int32_t n);
+int32_t soft_partial_stride();
+hipError_t soft_forward(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
+                        int32_t nbins, double r_c, double kappa, double *partial, double *gout,
+                        double *energy, hipStream_t stream);
+hipError_t soft_backward(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
+                         int32_t nbins, double r_c, double kappa, const double *dg,
+                         const double *dE, double *gpos, double *grad_r, hipStream_t stream);
+
 // Diagnostics of the device arithmetic (k_diag.hip).
 hipError_t diag_fp(const double *a, const double *b, int32_t n, double *sq, double *dv,
                    hipStream_t s);

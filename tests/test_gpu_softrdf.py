@@ -1,0 +1,164 @@
+"""GPU soft g(r) + overlap energy: forward against the FP64 oracle, the
+hand-written backward against the oracle gradient and central finite
+differences, the autograd front end, and steering with SRM sweeps."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import srm_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def soft():
+    import torch
+    import paper_2605_18254_amd as srm
+    from paper_2605_18254_amd import softrdf
+    srm.lib()
+    return torch, srm, softrdf
+
+
+def _state(oracle_lib, dim, n, f, seed):
+    w = srm_inputs.make("disks2d" if dim == 2 else "softrdf", n=n, seed=seed, f_target=f)
+    o = oracle_lib.Oracle.from_workload(w)
+    o.run(3000)
+    return w, o
+
+
+@pytest.mark.parametrize("dim,n", [(3, 3000), (2, 2500)])
+def test_forward_and_gradient_match_oracle(soft, oracle_lib, dim, n):
+    torch, srm, softrdf = soft
+    w, o = _state(oracle_lib, dim, n, 0.3, 40 + dim)
+    pos = o.soa()
+    radii = np.full(n, o.s) * 1.05
+    rc = 5.0 * o.s
+    kw = dict(dim=dim, nbins=64, r_c=rc)
+    g_ref, e_ref = oracle_lib.softrdf_forward(pos, radii, **kw)
+    ws = softrdf.SoftRDF(n, dim, rc, nbins=64)
+    tp = torch.from_numpy(pos).cuda()
+    tr = torch.from_numpy(radii).cuda()
+    g, e = ws.forward(tp, tr)
+    assert np.allclose(g.cpu().numpy(), g_ref, rtol=1e-12, atol=1e-12)
+    assert abs(float(e) - e_ref) <= 1e-12 * max(1.0, e_ref) and e_ref > 0
+    rng = np.random.default_rng(dim)
+    dg = rng.standard_normal(64)
+    dE = 0.61
+    gp_ref, gr_ref = oracle_lib.softrdf_gradient(pos, radii, dg, dE, **kw)
+    gp, gr = ws.backward(tp, tr, torch.from_numpy(dg).cuda(),
+                         torch.tensor(dE, dtype=torch.float64, device="cuda"))
+    scale = np.abs(gp_ref).max()
+    assert np.allclose(gp.cpu().numpy(), gp_ref, rtol=1e-10, atol=1e-12 * scale)
+    assert np.allclose(gr.cpu().numpy(), gr_ref, rtol=1e-10, atol=1e-14)
+    # deterministic: a second call is bit-identical
+    g2, e2 = ws.forward(tp, tr)
+    assert torch.equal(g, g2) and torch.equal(e, e2)
+    ws.close()
+
+
+def test_config5_central_differences(soft):
+    """N=2e5 spheres at f=0.30: 64 random coordinates, central differences
+    with h = 1e-6 against the hand-written backward."""
+    torch, srm, softrdf = soft
+    w = srm_inputs.make("softrdf")
+    g_ctx = srm.SRM.from_workload(w, device=True)
+    st, info = g_ctx.run(500)
+    assert st == 0
+    pos = torch.empty((3, w.n), dtype=torch.float64, device="cuda")
+    g_ctx.state_device(pos)
+    r = w.s_target
+    radii = torch.full((w.n,), r * 1.02, dtype=torch.float64, device="cuda")
+    ws = softrdf.SoftRDF(w.n, 3, 5.0 * r, nbins=64)
+    rng = np.random.default_rng(5)
+    dg = torch.from_numpy(rng.standard_normal(64)).cuda()
+    dE = torch.tensor(1.3, dtype=torch.float64, device="cuda")
+    gp, gr = ws.backward(pos, radii, dg, dE)
+
+    def L(p, rr):
+        g, e = ws.forward(p, rr)
+        return float((dg * g).sum() + dE * e)
+
+    h = 1e-6
+    worst = 0.0
+    for k in range(64):
+        a = int(rng.integers(0, 3))
+        i = int(rng.integers(0, w.n))
+        p1 = pos.clone()
+        p1[a, i] += h
+        p2 = pos.clone()
+        p2[a, i] -= h
+        fd = (L(p1, radii) - L(p2, radii)) / (2 * h)
+        an = float(gp[a, i])
+        err = abs(fd - an) / max(1.0, abs(an))
+        worst = max(worst, err)
+    _say(f"config 5: worst relative FD error over 64 coordinates {worst:.3g}")
+    assert worst < 1e-5
+    ws.close()
+    g_ctx.close()
+
+
+def test_poisson_gives_unit_g(soft):
+    torch, srm, softrdf = soft
+    n = 200000
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    pos = torch.rand((3, n), dtype=torch.float64, device="cuda", generator=gen)
+    radii = torch.zeros(n, dtype=torch.float64, device="cuda")
+    rc = 0.02
+    ws = softrdf.SoftRDF(n, 3, rc, nbins=64)
+    g, e = ws.forward(pos, radii)
+    mean = float(g[16:].mean())
+    _say(f"poisson mean g = {mean}")
+    assert abs(mean - 1.0) < 0.01 and float(e) == 0.0
+    ws.close()
+
+
+def test_autograd_chain_rule(soft):
+    torch, srm, softrdf = soft
+    rng = np.random.default_rng(8)
+    n = 4000
+    pos = torch.from_numpy(rng.random((3, n))).cuda().requires_grad_(True)
+    radii = torch.full((n,), 0.012, dtype=torch.float64, device="cuda").requires_grad_(True)
+    ws = softrdf.SoftRDF(n, 3, 0.06, nbins=32)
+    target = torch.linspace(0.5, 1.5, 32, dtype=torch.float64, device="cuda")
+    g, e = softrdf.soft_rdf(pos, radii, ws)
+    loss = ((g - target) ** 2).sum() + 0.3 * e
+    loss.backward()
+    dg = (2 * (g - target)).detach()
+    gp, gr = ws.backward(pos.detach(), radii.detach(), dg.contiguous(),
+                         torch.tensor(0.3, dtype=torch.float64, device="cuda"))
+    assert torch.allclose(pos.grad, gp, rtol=1e-12, atol=0)
+    assert torch.allclose(radii.grad, gr, rtol=1e-12, atol=0)
+    ws.close()
+
+
+def test_steering_keeps_zero_overlaps(soft):
+    """Steering toward a clustered (Thomas process) target: gradient steps
+    are taken, and every committed state has no overlapping pair."""
+    torch, srm, softrdf = soft
+    w = srm_inputs.make("softrdf", n=20000)
+    grow = srm.SRM.from_workload(w, device=True)
+    assert grow.run(500)[0] == 0
+    pos = torch.empty((3, w.n), dtype=torch.float64, device="cuda")
+    grow.state_device(pos)
+    grow.close()
+    r = w.s_target
+    ctx = srm.SRM(dim=3, n=w.n, s_target=r, c_w=0.0, c_m=w.c_m, n_k=8, n_l=8, seed=w.seed,
+                  pos=pos, s0=r, sweep0=1000)
+    nb = 64
+    ws = softrdf.SoftRDF(w.n, 3, 5.0 * r, nbins=nb)
+    centres = (torch.arange(nb, dtype=torch.float64, device="cuda") + 0.5) * (5.0 * r / nb)
+    target = softrdf.thomas_g(centres, 1e-3 * w.n, 3.0 * r)
+    target = torch.where(centres < 2 * r, torch.zeros_like(target), target)
+    hist = softrdf.steer(ctx, ws, target, r, steps=6, max_step=0.5 * w.c_m, lam=1.0)
+    _say(f"steering history {hist}")
+    assert any(acc for _, acc in hist)
+    assert all(math.isfinite(l) for l, _ in hist)
+    assert len(ctx.pairs(0.0)) == 0
+    ws.close()
+    ctx.close()
