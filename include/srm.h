@@ -212,6 +212,42 @@ srm_status srm_softrdf_backward(srm_soft *ctx, const double *pos, const double *
                                 double *grad_radii);
 srm_status srm_softrdf_free(srm_soft *ctx);
 
+/* ---- batched ensembles ------------------------------------------------- */
+
+/* `count` independent periodic boxes (RVEs) of balls, 2D and 3D mixed, each
+ * with its own srm_params (shape SRM_BALL, n_k >= 1), advanced together:
+ * the per-RVE Algorithm 1 state lives on the device and a captured hipGraph
+ * of batched kernels moves every unfinished RVE by a few passes per replay.
+ * pos: the RVEs' dim*n SoA blocks one after another (host); rho: their n
+ * shape radii one after another (host), or NULL for all 1.  All RVEs start
+ * at s = 0 with sweep counter 0.  Each RVE's result is bit-identical to
+ * srm_run_to_fraction on the same inputs. */
+typedef struct srm_batch srm_batch;
+
+typedef struct {
+    int64_t replays;        /* graph replays of this run */
+    int64_t slots;          /* pass slots (replays * slots per replay) */
+    int32_t converged;      /* RVEs at their target */
+    int32_t not_converged;  /* RVEs that used up max_sweeps */
+    int64_t passes;         /* migration passes summed over RVEs */
+    int64_t updates;        /* particle updates summed over RVEs */
+} srm_batch_info;
+
+srm_status srm_batch_init(int32_t count, const srm_params *params, const double *pos,
+                          const double *rho, srm_batch **out);
+/* Launch shape only (results do not depend on it): pass slots per graph
+ * replay (1..64) and threads per block of the migration kernels. */
+srm_status srm_batch_configure(srm_batch *b, int32_t slots_per_replay, int32_t block);
+/* Run until every RVE converged or used max_sweeps more sweeps
+ * (SRM_ENOTCONV then; converged RVEs keep their result). */
+srm_status srm_batch_run(srm_batch *b, int32_t max_sweeps, srm_batch_info *info);
+/* Committed state of RVE r: pos (dim*n, host, id order), s, sweep counter,
+ * passes run so far (all nullable). */
+srm_status srm_batch_get(srm_batch *b, int32_t r, double *pos, double *s, int64_t *sweep,
+                         int64_t *passes);
+srm_status srm_batch_free(srm_batch *b);
+const char *srm_batch_last_error(void);
+
 /* ---- device-time profile ------------------------------------------------ */
 
 /* Device time of the sweep's kernels, measured with hipEvents recorded on

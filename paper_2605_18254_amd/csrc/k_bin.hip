@@ -74,9 +74,10 @@ __global__ void __launch_bounds__(kBlock) k_bin_count(const double *__restrict__
     const unsigned long long heads = __ballot(head);
     const int nlive = __popcll(__ballot(live));  // live lanes are a prefix
     // first lane of this lane's run, and the run's end
-    const unsigned long long below = heads & ((2ull << lane) - 1ull);
+    const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const unsigned long long below = heads & upto;
     const int first = below ? 63 - __clzll(below) : lane;
-    const unsigned long long above = heads & ~((2ull << lane) - 1ull);
+    const unsigned long long above = heads & ~upto;
     int next = above ? __ffsll((long long)above) - 1 : 64;
     if (next > nlive) next = nlive;
     int32_t base = 0;

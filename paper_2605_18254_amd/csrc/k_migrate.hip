@@ -16,103 +16,13 @@
 // see a periodic image: neither the trial position nor any candidate has
 // wrapped, and all differences are below L/2, so the minimum-image
 // correction is the identity there and is skipped.
-#include "srm_internal.hpp"
+#include "srm_cellpass.hpp"
 
 namespace srm {
 
 namespace {
 
 constexpr int kBlock = 256;
-
-// Does a ball of radius Ri at (yx, yy, yz) overlap any particle of the
-// slices other than slot `self`?  q = (dx*dx + dy*dy) + dz*dz <= (Ri+Rj)^2.
-template <int DIM, bool POLY, bool GENERAL>
-__device__ __forceinline__ bool ball_hits(const PassArgs &a, const int32_t *lo, const int32_t *hi,
-                                          int32_t self, double yx, double yy, double yz, double Ri)
-{
-    const double *__restrict__ X = a.buf.x[0];
-    const double *__restrict__ Y = a.buf.x[1];
-    const double *__restrict__ Z = a.buf.x[2];
-#pragma unroll
-    for (int r = 0; r < Rows<DIM>::kRanges; ++r) {
-        for (int32_t q = lo[r]; q < hi[r]; ++q) {
-            if (q == self) continue;
-            double dx = yx - X[q];
-            double dy = yy - Y[q];
-            if (GENERAL) {
-                dx = min_image(dx, a.g.box[0], a.g.half[0]);
-                dy = min_image(dy, a.g.box[1], a.g.half[1]);
-            }
-            double qq = dx * dx + dy * dy;
-            if (DIM == 3) {
-                double dz = yz - Z[q];
-                if (GENERAL) dz = min_image(dz, a.g.box[2], a.g.half[2]);
-                qq = qq + dz * dz;
-            }
-            double sig2;
-            if (POLY) {
-                const double sig = Ri + a.s * a.buf.rho[q];
-                sig2 = sig * sig;
-            } else {
-                sig2 = a.sig2_mono;
-            }
-            if (qq <= sig2) return true;
-        }
-    }
-    return false;
-}
-
-template <int DIM>
-__device__ __forceinline__ bool is_interior(const Grid &g, int32_t cx, int32_t cy, int32_t cz)
-{
-    bool in = g.na[0] >= 8 && g.na[1] >= 8 && cx >= 2 && cx <= g.na[0] - 3 && cy >= 2 &&
-              cy <= g.na[1] - 3;
-    if (DIM == 3) in = in && g.na[2] >= 8 && cz >= 2 && cz <= g.na[2] - 3;
-    return in;
-}
-
-// Algorithm 3 for the particles of one cell (global-memory path): slots
-// [beg, end) in ascending id order, each with up to N_l trials.
-template <int DIM, bool POLY>
-__device__ __forceinline__ void migrate_cell_global(const PassArgs &a, int32_t cx, int32_t cy,
-                                                    int32_t cz)
-{
-    const int32_t c = cx + a.g.na[0] * (cy + a.g.na[1] * cz);
-    const int32_t beg = a.start[c], end = a.start[c + 1];
-    if (beg == end) return;
-    int32_t lo[Rows<DIM>::kRanges], hi[Rows<DIM>::kRanges];
-    stencil_slices<DIM>(a.g, a.start, cx, cy, cz, lo, hi);
-    const bool general = !is_interior<DIM>(a.g, cx, cy, cz);
-    double *__restrict__ X = a.buf.x[0];
-    double *__restrict__ Y = a.buf.x[1];
-    double *__restrict__ Z = a.buf.x[2];
-    for (int32_t p = beg; p < end; ++p) {
-        const double ox = X[p], oy = Y[p], oz = (DIM == 3) ? Z[p] : 0.0;
-        const uint32_t id = (uint32_t)a.buf.id[p];
-        const double Ri = POLY ? a.s * a.buf.rho[p] : a.s;
-        uint8_t code = 0;
-        Draw d = a.draw;
-        for (int32_t l = 1; l <= a.n_l; ++l) {
-            double v[3];
-            d.word = a.draw.word | ((uint32_t)l << 8);
-            unit_vector<DIM>(d, id, 0, a.c_m, v);
-            const double yx = wrap_coord(ox + v[0], a.g.box[0]);
-            const double yy = wrap_coord(oy + v[1], a.g.box[1]);
-            const double yz = (DIM == 3) ? wrap_coord(oz + v[2], a.g.box[2]) : 0.0;
-            const bool hit = general ? ball_hits<DIM, POLY, true>(a, lo, hi, p, yx, yy, yz, Ri)
-                                     : ball_hits<DIM, POLY, false>(a, lo, hi, p, yx, yy, yz, Ri);
-            if (!hit) {
-                X[p] = yx;
-                Y[p] = yy;
-                if (DIM == 3) Z[p] = yz;
-                code = (uint8_t)l;
-                break;
-            }
-        }
-        a.acc[p] = code;
-        if (code == 0) a.failed[1 + atomicAdd(&a.failed[0], 1)] = p;
-    }
-}
 
 // One thread per colour cell, candidates read from global memory (grids
 // too small for the tiled kernel).
@@ -611,20 +521,6 @@ __global__ void __launch_bounds__(64) k_migrate_overflow(PassArgs a, TileLattice
 // position and every later one at a position it kept if it was rejected).
 // So only particles with accept code 0 are tested; check_all tests every
 // particle (initial-state validation).
-template <int DIM, bool POLY>
-__device__ __forceinline__ bool check_ball_one(const PassArgs &a, int32_t p)
-{
-    const double x = a.buf.x[0][p], y = a.buf.x[1][p];
-    const double z = (DIM == 3) ? a.buf.x[2][p] : 0.0;
-    const int32_t cx = cell_coord(x, a.g.inv_w[0], a.g.na[0]);
-    const int32_t cy = cell_coord(y, a.g.inv_w[1], a.g.na[1]);
-    const int32_t cz = (DIM == 3) ? cell_coord(z, a.g.inv_w[2], a.g.na[2]) : 0;
-    int32_t lo[Rows<DIM>::kRanges], hi[Rows<DIM>::kRanges];
-    stencil_slices<DIM>(a.g, a.start, cx, cy, cz, lo, hi);
-    const double Ri = POLY ? a.s * a.buf.rho[p] : a.s;
-    return ball_hits<DIM, POLY, true>(a, lo, hi, p, x, y, z, Ri);
-}
-
 template <int DIM, bool POLY>
 __global__ void __launch_bounds__(kBlock) k_check_ball(PassArgs a, int32_t check_all, Counters *cnt)
 {

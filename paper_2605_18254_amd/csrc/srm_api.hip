@@ -152,44 +152,11 @@ struct srm_ctx {
 
 namespace {
 
-// Largest even m with m^dim <= n (caps the cell count near n for tiny radii).
-int64_t cell_cap(int dim, int64_t n)
-{
-    int64_t m = 0;
-    for (;;) {
-        const int64_t c = m + 2;
-        int64_t pw = 1;
-        for (int a = 0; a < dim; ++a) pw *= c;
-        if (pw > n) break;
-        m = c;
-    }
-    return m;
-}
+int64_t cell_cap(int dim, int64_t n) { return even_cap(dim, n); }
 
-// Adaptive grid of Algorithm 1 for the largest radius rmax: cell edge
-// cs = 2.5 rmax + 2.5 c_m; per axis N_a = m - (m mod 2) cells if
-// m = min(floor(L_a / cs), ncap) >= 4, else one cell.
 Grid make_grid(const srm_ctx *c, double rmax)
 {
-    Grid g{};
-    const double cs = 2.5 * rmax + 2.5 * c->p.c_m;
-    for (int a = 0; a < 3; ++a) {
-        g.box[a] = c->p.box[a];
-        g.half[a] = 0.5 * c->p.box[a];
-        if (a >= c->dim) {
-            g.na[a] = 1;
-            g.inv_w[a] = 1.0 / c->p.box[a];
-            continue;
-        }
-        int64_t m;
-        const double q = (cs > 0.0) ? c->p.box[a] / cs : 0.0;
-        if (!(cs > 0.0) || q >= (double)c->ncap) m = c->ncap;
-        else m = (int64_t)q;
-        g.na[a] = (int32_t)((m >= 4) ? m - (m & 1) : 1);
-        g.inv_w[a] = (double)g.na[a] / c->p.box[a];
-    }
-    g.ncell = g.na[0] * g.na[1] * g.na[2];
-    return g;
+    return sweep_grid(c->dim, c->p.box, c->ncap, c->p.c_m, rmax);
 }
 
 double fraction_at(const srm_ctx *c, double s)
@@ -204,12 +171,7 @@ double fraction_at(const srm_ctx *c, double s)
     return coeff * sd * c->sum_rho_d / vbox;
 }
 
-double swell(const srm_ctx *c, double s)
-{
-    const double ds = c->p.c_w * c->p.s_target;
-    const double s1 = s + ds;
-    return (s1 < c->p.s_target) ? s1 : c->p.s_target;
-}
+double swell(const srm_ctx *c, double s) { return swell_scale(s, c->p.c_w, c->p.s_target); }
 
 hipError_t alloc_buf(srm_ctx *c, PBuf &b)
 {

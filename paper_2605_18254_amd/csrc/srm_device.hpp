@@ -175,6 +175,55 @@ __device__ __forceinline__ bool disks_intersect(double dx, double dy, double dz,
     return D * D <= (4.0 * Ap) * Bp;
 }
 
+// Adaptive grid of Algorithm 1 for the largest radius rmax: cell edge
+// cs = 2.5 rmax + 2.5 c_m; per axis N_a = m - (m mod 2) cells if
+// m = min(floor(L_a / cs), ncap) >= 4, else one cell.  The same IEEE
+// operations on the host and on the device.
+__host__ __device__ __forceinline__ Grid sweep_grid(int dim, const double box[3], int64_t ncap,
+                                                    double c_m, double rmax)
+{
+    Grid g{};
+    const double cs = 2.5 * rmax + 2.5 * c_m;
+    for (int a = 0; a < 3; ++a) {
+        g.box[a] = box[a];
+        g.half[a] = 0.5 * box[a];
+        if (a >= dim) {
+            g.na[a] = 1;
+            g.inv_w[a] = 1.0 / box[a];
+            continue;
+        }
+        int64_t m;
+        const double q = (cs > 0.0) ? box[a] / cs : 0.0;
+        if (!(cs > 0.0) || q >= (double)ncap) m = ncap;
+        else m = (int64_t)q;
+        g.na[a] = (int32_t)((m >= 4) ? m - (m & 1) : 1);
+        g.inv_w[a] = (double)g.na[a] / box[a];
+    }
+    g.ncell = g.na[0] * g.na[1] * g.na[2];
+    return g;
+}
+
+// Swelling step: s' = min(s + c_w s_target, s_target).
+__host__ __device__ __forceinline__ double swell_scale(double s, double c_w, double s_target)
+{
+    const double s1 = s + c_w * s_target;
+    return (s1 < s_target) ? s1 : s_target;
+}
+
+// Largest even m with m^dim <= n.
+__host__ __device__ __forceinline__ int64_t even_cap(int dim, int64_t n)
+{
+    int64_t m = 0;
+    for (;;) {
+        const int64_t c = m + 2;
+        int64_t pw = 1;
+        for (int a = 0; a < dim; ++a) pw *= c;
+        if (pw > n) break;
+        m = c;
+    }
+    return m;
+}
+
 // Slices of a cell-sorted array covering the 3^dim cells around a cell.
 template <int DIM>
 struct Rows {

@@ -363,3 +363,51 @@ def test_rdf_counts_match_oracle(srm, oracle_lib, dim, n, nbins):
     ideal = 0.5 * n * (n - 1) * shell
     assert np.allclose(gr, counts / ideal, rtol=1e-12)
     g.close()
+
+
+# ------------------------------------------------------------ batched RVEs
+
+def test_batch_members_bitidentical_to_solo_runs(srm, oracle_lib):
+    """A reduced ensemble (half 2D, half 3D, lognormal radii, uneven N and
+    targets) in one batched run: every RVE equals its solo run bit for bit,
+    and two of them equal the oracle."""
+    from paper_2605_18254_amd.batch import Batch
+    metas = srm_inputs.batch_members(count=12, n_scale=0.02)
+    ws = [srm_inputs.make_member(m) for m in metas]
+    b = Batch(ws)
+    b.configure(3, 128)
+    st, info = b.run(600)
+    _say(f"batch: {info}")
+    assert st == 0 and info["converged"] == len(ws)
+    for r, w in enumerate(ws):
+        pos_b, s_b, t_b, passes_b = b.get(r)
+        g = srm.SRM.from_workload(w)
+        st_s, inf = g.run(600)
+        assert st_s == 0
+        pos_s, _, s_s, t_s = g.state()
+        assert np.array_equal(pos_b, pos_s), r
+        assert s_b == s_s == w.s_target and t_b == t_s and passes_b == inf["passes"]
+        g.close()
+    for r in (0, len(ws) - 1):
+        o = oracle_lib.Oracle.from_workload(ws[r])
+        assert o.run(600)[0] == 0
+        assert np.array_equal(b.get(r)[0], o.soa())
+    b.close()
+
+
+def test_batch_launch_shape_invariance_and_notconv(srm):
+    from paper_2605_18254_amd.batch import Batch
+    metas = srm_inputs.batch_members(count=6, n_scale=0.03, seed0=2000)
+    ws = [srm_inputs.make_member(m) for m in metas]
+    res = []
+    for slots, block in [(1, 64), (5, 256)]:
+        b = Batch(ws)
+        b.configure(slots, block)
+        st, info = b.run(10)           # stops early: not converged yet
+        assert st == srm.ENOTCONV and info["not_converged"] == len(ws)
+        st, info = b.run(600)          # continues to the target
+        assert st == 0
+        res.append([b.get(r)[0] for r in range(len(ws))])
+        b.close()
+    for a_, b_ in zip(*res):
+        assert np.array_equal(a_, b_)
