@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-fraction", type=float, default=0.25,
                     help="fraction of the cell layers the oracle sample covers")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-ensemble and gradient measurements")
+    ap.add_argument("--batch-sweeps", type=int, default=400,
+                    help="sweep budget of every RVE of the batched ensemble")
     return ap.parse_args()
 
 
@@ -67,6 +71,155 @@ def cpu_baseline(w, frac):
                 sample=f"sweep 1, pass 1 of the same N={w.n} workload restricted to "
                        f"{layers}/{nz} cell layers ({updates} particle updates, "
                        f"{dt:.1f} s incl. binning all N), single-threaded C oracle")
+
+
+def _say(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def batched_extra(max_sweeps):
+    """The 256-RVE ensemble (half 2D, half 3D, N log-uniform in [1e3, 1e5],
+    targets uniform in [0.30, 0.55], lognormal radii, seeds 1000..1255):
+    one batched run against the 256 solo runs, same sweep budget.  Both do
+    the same passes (the states are compared bit for bit), so the ratio of
+    wall times is the batching gain."""
+    import numpy as np
+    import torch
+
+    import paper_2605_18254_amd as srm
+    import srm_inputs
+    from paper_2605_18254_amd.batch import Batch, autotune
+
+    ws = [srm_inputs.make_member(m) for m in srm_inputs.batch_members()]
+    t0 = time.perf_counter()
+    shape = autotune(ws, sweeps=20, slots=(2, 4, 8), blocks=(64, 128, 256))
+    tune_s = time.perf_counter() - t0
+    _say(f"batch autotune -> slots={shape[0]} block={shape[1]} ({tune_s:.1f} s)")
+    b = Batch(ws)
+    b.configure(*shape)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, info = b.run(max_sweeps)
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    _say(f"batched: {dt_b:.2f} s, {info}")
+    ctxs = [srm.SRM.from_workload(w, device=True) for w in ws]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    upd_s = 0
+    for r, g in enumerate(ctxs):
+        upd_s += g.run(max_sweeps)[1]["updates"]
+        if r % 32 == 31:
+            _say(f"sequential: {r + 1} RVEs, {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    dt_s = time.perf_counter() - t0
+    _say(f"sequential: {dt_s:.2f} s")
+    identical, overlaps, fr_b = True, 0, []
+    for r, g in enumerate(ctxs):
+        pos_b, s_b, t_b, _ = b.get(r)
+        pos_s, _, s_s, t_s = g.state()
+        identical = identical and np.array_equal(pos_b, pos_s) and s_b == s_s and t_b == t_s
+        overlaps += len(g.pairs(0.0))
+        fr_b.append(s_b / ws[r].s_target)
+        g.close()
+    b.close()
+    return {
+        "workload": "256 RVEs: 128 2D + 128 3D, N log-uniform [1e3,1e5], f uniform "
+                    "[0.30,0.55], lognormal radii sigma 0.2, seeds 1000..1255",
+        "max_sweeps": max_sweeps, "converged": info["converged"],
+        "not_converged": info["not_converged"],
+        "min_s_over_s_target": min(fr_b), "overlapping_pairs": overlaps,
+        "bitidentical_to_solo": identical, "launch": {"slots": shape[0], "block": shape[1]},
+        "updates": info["updates"],
+        "batched": {"s": dt_b, "updates_per_s": info["updates"] / dt_b,
+                    "graph_replays": info["replays"]},
+        "sequential": {"s": dt_s, "updates_per_s": upd_s / dt_s},
+        "speedup": dt_s / dt_b,
+    }
+
+
+def grad_extra(steps, steer_steps):
+    """Soft g(r) (64 Gaussian bins up to 5r) + overlap energy, forward and
+    hand-written backward, on N = 2e5 spheres grown by SRM to f = 0.30; then
+    steering toward a Thomas-process target with an SRM sweep after each
+    gradient step."""
+    import torch
+
+    import paper_2605_18254_amd as srm
+    import srm_inputs
+    from paper_2605_18254_amd import softrdf
+
+    w = srm_inputs.make("softrdf")
+    grow = srm.SRM.from_workload(w, device=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, run = grow.run(3000)
+    torch.cuda.synchronize()
+    dt_grow = time.perf_counter() - t0
+    pos = torch.empty((3, w.n), dtype=torch.float64, device="cuda")
+    grow.state_device(pos)
+    r = w.s_target
+    nb, r_c = 64, 5.0 * r
+    counts, _ = grow.rdf(1, r_c + 4.0 * r_c / nb)
+    pairs = int(counts.sum())
+    grow.close()
+    ws = softrdf.SoftRDF(w.n, 3, r_c, nbins=nb)
+    radii = torch.full((w.n,), r, dtype=torch.float64, device="cuda")
+    centres = (torch.arange(nb, dtype=torch.float64, device="cuda") + 0.5) * (r_c / nb)
+    target = softrdf.thomas_g(centres, 1e-3 * w.n, 3.0 * r)
+    target = torch.where(centres < 2 * r, torch.zeros_like(target), target)
+    p = pos.clone().requires_grad_(True)
+
+    def step():
+        g, e = softrdf.soft_rdf(p, radii, ws)
+        loss = ((g - target) ** 2).sum() + e
+        p.grad = None
+        loss.backward()
+        return loss
+
+    for _ in range(2):
+        step()
+    fwd0, fwd1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    fwd0.record()
+    for _ in range(steps):
+        softrdf.soft_rdf(p.detach(), radii, ws)
+    fwd1.record()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    for _ in range(steps):
+        loss = step()
+    s1.record()
+    torch.cuda.synchronize()
+    ms_fwd = fwd0.elapsed_time(fwd1) / steps
+    ms_step = s0.elapsed_time(s1) / steps
+    ctx = srm.SRM(dim=3, n=w.n, s_target=r, c_w=0.0, c_m=w.c_m, n_k=8, n_l=8, seed=w.seed,
+                  pos=pos, s0=r, sweep0=run["sweeps"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = softrdf.steer(ctx, ws, target, r, steps=steer_steps, max_step=0.5 * w.c_m)
+    torch.cuda.synchronize()
+    dt_steer = time.perf_counter() - t0
+    _, _, s_fin, _ = ctx.state()
+    overlaps = len(ctx.pairs(0.0))
+    ctx.close()
+    ws.close()
+    return {
+        "workload": "spheres3d N=2e5 f=0.30 seed 3; soft g(r) 64 bins on [0, 5r], h = bin "
+                    "width, C2 taper to 5r+4h; target Thomas process (parent density "
+                    "1e-3 N, sigma 3r); loss |g - target|^2 + E",
+        "grow_to_fraction": {"s": dt_grow, "sweeps": run["sweeps"],
+                             "updates_per_s": run["updates"] / dt_grow,
+                             "fraction": run["fraction"]},
+        "pairs_within_cutoff": pairs,
+        "ms_forward": ms_fwd, "ms_forward_backward": ms_step,
+        "pair_evals_per_s": 3 * pairs / (ms_step / 1e3),
+        "steer": {"steps": steer_steps, "s": dt_steer,
+                  "ms_per_step": dt_steer / steer_steps * 1e3,
+                  "accepted": sum(1 for _, a in hist if a),
+                  "loss_first": hist[0][0], "loss_last": hist[-1][0],
+                  "s_over_s_target": s_fin / r, "overlapping_pairs": overlaps},
+    }
 
 
 def main():
@@ -126,7 +279,7 @@ def main():
                    "final_sweep": final["sweep"], "grid": list(final["grid"])},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_migrate_ball<3,false> (one colour phase per launch)",
+                     "kernel": "k_migrate_tile<3,false> + k_migrate_overflow<3,false> (one colour phase)",
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "bytes_per_update": MIGRATE_BYTES},
         "kernel_ms": {"bin": prof["ms_bin"], "migrate": mig_ms, "check": prof["ms_check"],
@@ -135,6 +288,9 @@ def main():
                       "achieved_gbs": (MIGRATE_BYTES + BIN_BYTES) * updates / dt / 1e9,
                       "frac": (MIGRATE_BYTES + BIN_BYTES) * updates / dt / 1e9 / HBM_PEAK_GBS},
     }
+    if not args.no_extras:
+        out["extras"] = {"batched": batched_extra(args.batch_sweeps),
+                         "gradient": grad_extra(20, 10)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_fraction)
     print(json.dumps(out), flush=True)

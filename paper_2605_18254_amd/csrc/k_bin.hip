@@ -254,6 +254,46 @@ __global__ void __launch_bounds__(kBlock) k_fixup(PBuf b, int dim, const int32_t
     }
 }
 
+// Crowded grids place particles by rank instead of sorting afterwards: the
+// ids go to their cells in arrival order, then each particle counts the
+// smaller ids of its cell (its place in ascending id order) and moves its
+// record there.
+__global__ void __launch_bounds__(kBlock) k_scatter_id(const int32_t *__restrict__ id, int32_t n,
+                                                       const int32_t *__restrict__ cell,
+                                                       const int32_t *__restrict__ slot,
+                                                       const int32_t *__restrict__ start,
+                                                       int32_t *__restrict__ tmpid)
+{
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    tmpid[start[cell[p]] + slot[p]] = id[p];
+}
+
+__global__ void __launch_bounds__(kBlock) k_rank_scatter(PBuf src, PBuf dst, int32_t n, int dim,
+                                                         const int32_t *__restrict__ cell,
+                                                         const int32_t *__restrict__ start,
+                                                         const int32_t *__restrict__ tmpid)
+{
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t c = cell[p];
+    const int32_t b = start[c], e = start[c + 1];
+    const int32_t me = src.id[p];
+    int32_t rank = 0;
+    for (int32_t q = b; q < e; ++q) rank += tmpid[q] < me;
+    const int32_t d = b + rank;
+    dst.x[0][d] = src.x[0][p];
+    dst.x[1][d] = src.x[1][p];
+    if (dim == 3) dst.x[2][d] = src.x[2][p];
+    dst.id[d] = me;
+    if (src.rho) dst.rho[d] = src.rho[p];
+    if (src.nrm[0]) {
+        dst.nrm[0][d] = src.nrm[0][p];
+        dst.nrm[1][d] = src.nrm[1][p];
+        dst.nrm[2][d] = src.nrm[2][p];
+    }
+}
+
 struct XPtrs {
     const double *x[6];
 };
@@ -335,6 +375,9 @@ hipError_t scan_counts(const int32_t *counts, int32_t *start, int32_t *partials,
     return hipGetLastError();
 }
 
+// Mean particles per cell from which the rank placement replaces the sort.
+constexpr int64_t kRankOccupancy = 3;
+
 hipError_t bin_particles(int dim, const PBuf &src, const PBuf &dst, int32_t n, const Grid &g,
                          Scratch &sc, Counters *cnt, hipStream_t stream)
 {
@@ -353,7 +396,12 @@ hipError_t bin_particles(int dim, const PBuf &src, const PBuf &dst, int32_t n, c
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = scan_counts(sc.counts, sc.start, sc.partials, g.ncell, stream)) != hipSuccess) return e;
-    if (n > 0) {
+    if (n > 0 && sc.tmpid && (int64_t)n >= kRankOccupancy * (int64_t)g.ncell) {
+        hipLaunchKernelGGL(k_scatter_id, dim3(blocks_for(n)), dim3(kBlock), 0, stream, src.id, n,
+                           sc.cell, sc.slot, sc.start, sc.tmpid);
+        hipLaunchKernelGGL(k_rank_scatter, dim3(blocks_for(n)), dim3(kBlock), 0, stream, src, dst,
+                           n, dim, sc.cell, sc.start, sc.tmpid);
+    } else if (n > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(kBlock), 0, stream, src, dst, n,
                            dim, sc.cell, sc.slot, sc.start);
         hipLaunchKernelGGL(k_fixup, dim3(blocks_for(g.ncell)), dim3(kBlock), 0, stream, dst, dim,

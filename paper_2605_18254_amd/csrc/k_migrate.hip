@@ -39,6 +39,20 @@ __global__ void __launch_bounds__(kBlock) k_migrate_ball(PassArgs a, ColourLatti
                                    (DIM == 3) ? 2 * jz + L.off[2] : 0);
 }
 
+// One 64-thread workgroup per colour cell (crowded cells).
+template <int DIM, bool POLY>
+__global__ void __launch_bounds__(64) k_migrate_wave(PassArgs a, ColourLattice L)
+{
+    __shared__ WaveLds lds;
+    const int32_t t = blockIdx.x;
+    const int32_t jx = t % L.h[0];
+    const int32_t r1 = t / L.h[0];
+    const int32_t jy = r1 % L.h[1];
+    const int32_t jz = r1 / L.h[1];
+    migrate_cell_wave<DIM, POLY>(a, 2 * jx + L.off[0], 2 * jy + L.off[1],
+                                 (DIM == 3) ? 2 * jz + L.off[2] : 0, lds);
+}
+
 // ------------------------------------------------------------ tiled kernel
 //
 // A 256-thread workgroup owns a tile of 64 cells of the launch's colour
@@ -687,12 +701,33 @@ bool tile_ok(int dim, const Grid &g)
 
 }  // namespace
 
+// Crowded grids (mean occupancy of at least kWaveOccupancy particles per
+// cell) migrate with one wavefront per cell.
+bool wave_cells(int dim, const Grid &g, int32_t n)
+{
+    int64_t ncell = 1;
+    for (int ax = 0; ax < dim; ++ax) ncell *= g.na[ax];
+    return (int64_t)n >= (int64_t)kWaveOccupancy * ncell;
+}
+
 hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int colour,
                           hipStream_t stream, bool *launched)
 {
     ColourLattice L;
     *launched = false;
     if (!colour_lattice(dim, a.g, colour, L)) return hipSuccess;
+    if (shape != SRM_PLATELET && wave_cells(dim, a.g, a.n)) {
+        const dim3 grid(L.count), block(64);
+        if (dim == 3) {
+            if (poly) hipLaunchKernelGGL((k_migrate_wave<3, true>), grid, block, 0, stream, a, L);
+            else hipLaunchKernelGGL((k_migrate_wave<3, false>), grid, block, 0, stream, a, L);
+        } else {
+            if (poly) hipLaunchKernelGGL((k_migrate_wave<2, true>), grid, block, 0, stream, a, L);
+            else hipLaunchKernelGGL((k_migrate_wave<2, false>), grid, block, 0, stream, a, L);
+        }
+        *launched = true;
+        return hipGetLastError();
+    }
     if (shape != SRM_PLATELET && a.ovf && tile_ok(dim, a.g)) {
         TileLattice T{};
         const int tsz = (dim == 3) ? 4 : 8;

@@ -314,6 +314,7 @@ srm_status srm_init(const srm_params *p, const double *pos, const double *rho,
     hipError_t e = hipSuccess;
     if ((e = alloc_buf(c, c->P)) || (e = alloc_buf(c, c->Q)) || (e = alloc_buf(c, c->T)) ||
         (e = c->alloc(&c->sc.cell, n)) || (e = c->alloc(&c->sc.slot, n)) ||
+        (e = c->alloc(&c->sc.tmpid, n)) ||
         (e = c->alloc(&c->acc, n)) || (e = c->alloc(&c->dtmp, 3 * n)) ||
         (e = c->alloc(&c->itmp, n)) || (e = c->alloc(&c->dcnt, 1)))
         return bail(fail(SRM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
@@ -894,6 +895,7 @@ srm_status srm_softrdf_create(const srm_softrdf_params *p, int64_t n, void *stre
     c->sc.cap = n + 2;
     if (!e) e = c->alloc(&c->sc.cell, n);
     if (!e) e = c->alloc(&c->sc.slot, n);
+    if (!e) e = c->alloc(&c->sc.tmpid, n);
     if (!e) e = c->alloc(&c->sc.counts, (size_t)c->sc.cap);
     if (!e) e = c->alloc(&c->sc.start, (size_t)c->sc.cap + 1);
     if (!e) e = c->alloc(&c->sc.partials, (size_t)(c->sc.cap / 2048 + 2));

@@ -34,6 +34,7 @@ namespace srm {
 namespace {
 
 constexpr int kB = 256;
+constexpr int32_t kWaveGrid = 8192;  // workgroups of a wavefront-per-cell launch
 
 enum : int32_t { kSweepStart = 0, kMain = 1, kShake = 2, kDone = 3, kNotConv = 4 };
 enum : int32_t { kRoleP = 0, kRoleQ = 1, kRoleT = 2 };
@@ -52,7 +53,7 @@ struct Rve {
     int32_t mode, k, sweeps, passes, shakes, max_sweeps;
     int32_t role[3];
     int32_t active, src, dst, kind;
-    int32_t overlap, pad1;
+    int32_t overlap, wave;  // wave: crowded grid, one wavefront per cell
     Grid g;
     int32_t ccount[8];
 };
@@ -69,9 +70,10 @@ struct BatchDev {
     int32_t *rve_of;       // particle slot -> RVE
     int32_t *rve_of_cell;  // cell slot -> RVE
     int32_t *cell, *slot, *counts, *start, *partials;
+    int32_t *tmpid;        // ids scattered in arrival order, for the in-cell ranks
     uint8_t *acc;
     int32_t *failed;       // [0] count, then global slots
-    int32_t *prefix;       // [2 classes][8 colours][count + 1]
+    int32_t *prefix;       // [4 classes (dim, wave)][8 colours][count + 1]
     int32_t *remaining;
 };
 
@@ -138,6 +140,9 @@ __global__ void k_ctl_begin(BatchDev d)
             }
             r.ccount[c] = (c < (1 << r.dim)) ? cnt : 0;
         }
+        int64_t ncell = 1;
+        for (int ax = 0; ax < r.dim; ++ax) ncell *= r.g.na[ax];
+        r.wave = (int64_t)r.n >= (int64_t)kWaveOccupancy * ncell;
         r.mode = kMain;
         r.k = 1;
     }
@@ -164,18 +169,20 @@ __global__ void k_ctl_begin(BatchDev d)
     r.active = 1;
 }
 
-// Prefix sums over RVEs of the colour cells of each (dimension, colour).
+// Prefix sums over RVEs of the colour cells of each class (dimension, one
+// thread or one wavefront per cell) and colour.
 __global__ void k_ctl_prefix(BatchDev d)
 {
     const int j = threadIdx.x;  // class * 8 + colour
-    if (j >= 16) return;
-    const int dim = (j < 8) ? 2 : 3, colour = j & 7;
+    if (j >= 32) return;
+    const int cls = j >> 3, colour = j & 7;
+    const int dim = (cls >> 1) ? 3 : 2, wave = cls & 1;
     int32_t *pre = d.prefix + (size_t)j * (d.count + 1);
     int32_t run = 0;
     for (int32_t i = 0; i < d.count; ++i) {
         pre[i] = run;
         const Rve &r = d.rve[i];
-        if (r.active && r.dim == dim) run += r.ccount[colour];
+        if (r.active && r.dim == dim && r.wave == wave) run += r.ccount[colour];
     }
     pre[d.count] = run;
 }
@@ -280,63 +287,43 @@ __global__ void __launch_bounds__(kB) k_bcount(BatchDev d)
     d.slot[p] = base + (lane - first);
 }
 
-__global__ void __launch_bounds__(kB) k_bscatter(BatchDev d)
+// Counting-sort placement without a sort pass: ids go to their cells in
+// arrival order first, then every particle counts the smaller ids of its
+// cell -- its rank in ascending id order -- and moves its record there.
+__global__ void __launch_bounds__(kB) k_bscatter_id(BatchDev d)
+{
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= d.ntotal) return;
+    const Rve &r = d.rve[d.rve_of[p]];
+    if (!r.active) return;
+    d.tmpid[d.start[d.cell[p]] + d.slot[p]] = d.id[r.src][p];
+}
+
+__global__ void __launch_bounds__(kB) k_brank(BatchDev d)
 {
     const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= d.ntotal) return;
     const Rve &r = d.rve[d.rve_of[p]];
     if (!r.active) return;
     const int s = r.src, t = r.dst;
-    const int32_t q = d.start[d.cell[p]] + d.slot[p];
+    const int32_t c = d.cell[p];
+    const int32_t b = d.start[c], e = d.start[c + 1];
+    const int32_t me = d.id[s][p];
+    int32_t rank = 0;
+    for (int32_t q = b; q < e; ++q) rank += d.tmpid[q] < me;
+    const int32_t q = b + rank;
     d.x[t][0][q] = d.x[s][0][p];
     d.x[t][1][q] = d.x[s][1][p];
     if (r.dim == 3) d.x[t][2][q] = d.x[s][2][p];
-    d.id[t][q] = d.id[s][p];
+    d.id[t][q] = me;
     if (r.poly) d.rho[t][q] = d.rho[s][p];
 }
-
-__global__ void __launch_bounds__(kB) k_bfixup(BatchDev d)
-{
-    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.ncells) return;
-    const Rve &r = d.rve[d.rve_of_cell[c]];
-    if (!r.active || c - r.coff >= r.g.ncell) return;
-    const int t = r.dst;
-    const int32_t beg = d.start[c], end = d.start[c + 1];
-    if (end - beg < 2) return;
-    int32_t *id = d.id[t];
-    double *x = d.x[t][0], *y = d.x[t][1], *z = d.x[t][2], *rho = d.rho[t];
-    bool sorted = true;
-    for (int32_t i = beg + 1; i < end; ++i) sorted = sorted && (id[i - 1] < id[i]);
-    if (sorted) return;
-    for (int32_t i = beg + 1; i < end; ++i) {
-        const int32_t key = id[i];
-        const double kx = x[i], ky = y[i], kz = (r.dim == 3) ? z[i] : 0.0;
-        const double kr = r.poly ? rho[i] : 0.0;
-        int32_t j = i - 1;
-        while (j >= beg && id[j] > key) {
-            id[j + 1] = id[j];
-            x[j + 1] = x[j];
-            y[j + 1] = y[j];
-            if (r.dim == 3) z[j + 1] = z[j];
-            if (r.poly) rho[j + 1] = rho[j];
-            --j;
-        }
-        id[j + 1] = key;
-        x[j + 1] = kx;
-        y[j + 1] = ky;
-        if (r.dim == 3) z[j + 1] = kz;
-        if (r.poly) rho[j + 1] = kr;
-    }
-}
-
-// ---- batched migration and check -------------------------------------------
 
 // One thread per colour cell of every active RVE of dimension DIM.
 template <int DIM, bool POLY>
 __global__ void __launch_bounds__(kB) k_bmigrate(BatchDev d, int colour)
 {
-    const int32_t *pre = d.prefix + (size_t)((DIM == 3 ? 8 : 0) + colour) * (d.count + 1);
+    const int32_t *pre = d.prefix + (size_t)((DIM == 3 ? 16 : 0) + colour) * (d.count + 1);
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= pre[d.count]) return;
     int32_t lo = 0, hi = d.count - 1;  // last RVE with pre[i] <= t
@@ -359,6 +346,37 @@ __global__ void __launch_bounds__(kB) k_bmigrate(BatchDev d, int colour)
                                    (DIM == 3) ? 2 * jz + off[2] : 0);
 }
 
+// One 64-thread workgroup per colour cell of every active RVE of dimension
+// DIM whose grid is crowded (grid-stride over those cells).
+template <int DIM, bool POLY>
+__global__ void __launch_bounds__(64) k_bmigrate_wave(BatchDev d, int colour)
+{
+    __shared__ WaveLds lds;
+    const int32_t *pre = d.prefix + (size_t)((DIM == 3 ? 24 : 8) + colour) * (d.count + 1);
+    const int32_t total = pre[d.count];
+    for (int32_t t = blockIdx.x; t < total; t += gridDim.x) {
+        int32_t lo = 0, hi = d.count - 1;  // last RVE with pre[i] <= t
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const Rve &r = d.rve[lo];
+        const int32_t u = t - pre[lo];
+        int32_t h[3], off[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            const bool split = ax < DIM && r.g.na[ax] >= 4;
+            h[ax] = split ? r.g.na[ax] / 2 : 1;
+            off[ax] = split ? (colour >> ax) & 1 : 0;
+        }
+        const int32_t jx = u % h[0], jy = (u / h[0]) % h[1], jz = u / (h[0] * h[1]);
+        const PassArgs a = pass_args_of(d, r);
+        migrate_cell_wave<DIM, POLY>(a, 2 * jx + off[0], 2 * jy + off[1],
+                                     (DIM == 3) ? 2 * jz + off[2] : 0, lds);
+        __syncthreads();  // LDS is reused by the next cell
+    }
+}
+
 template <bool POLY>
 __global__ void __launch_bounds__(kB) k_bcheck(BatchDev d)
 {
@@ -367,6 +385,7 @@ __global__ void __launch_bounds__(kB) k_bcheck(BatchDev d)
          i += gridDim.x * blockDim.x) {
         const int32_t p = d.failed[1 + i];
         Rve &r = d.rve[d.rve_of[p]];
+        if (__atomic_load_n(&r.overlap, __ATOMIC_RELAXED)) continue;  // already known
         const PassArgs a = pass_args_of(d, r);
         const bool hit = (r.dim == 3) ? check_ball_one<3, POLY>(a, p)
                                       : check_ball_one<2, POLY>(a, p);
@@ -449,21 +468,33 @@ hipError_t enqueue_slot(BatchHost *h)
     hipLaunchKernelGGL(k_bcount, dim3(nblk(d.ntotal)), dim3(kB), 0, s, d);
     hipError_t e = scan_counts(d.counts, d.start, d.partials, d.ncells, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bscatter, dim3(nblk(d.ntotal)), dim3(kB), 0, s, d);
-    hipLaunchKernelGGL(k_bfixup, dim3(nblk(d.ncells)), dim3(kB), 0, s, d);
+    hipLaunchKernelGGL(k_bscatter_id, dim3(nblk(d.ntotal)), dim3(kB), 0, s, d);
+    hipLaunchKernelGGL(k_brank, dim3(nblk(d.ntotal)), dim3(kB), 0, s, d);
     // Algorithm 3 over the colour schedule, per dimension class
     hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, s, d.failed);
     for (int dc = 0; dc < 2; ++dc) {
         const int dim = dc ? 3 : 2;
         if (h->bound[dc] == 0) continue;
         const dim3 grid(nblk(h->bound[dc], h->block)), block(h->block);
+        const dim3 wgrid(h->bound[dc] < kWaveGrid ? h->bound[dc] : kWaveGrid), wblock(64);
         for (int colour = 0; colour < (1 << dim); ++colour) {
+            // sparse grids: a thread per cell; crowded grids: a wavefront per cell
             if (dim == 3) {
-                if (h->poly) hipLaunchKernelGGL((k_bmigrate<3, true>), grid, block, 0, s, d, colour);
-                else hipLaunchKernelGGL((k_bmigrate<3, false>), grid, block, 0, s, d, colour);
+                if (h->poly) {
+                    hipLaunchKernelGGL((k_bmigrate<3, true>), grid, block, 0, s, d, colour);
+                    hipLaunchKernelGGL((k_bmigrate_wave<3, true>), wgrid, wblock, 0, s, d, colour);
+                } else {
+                    hipLaunchKernelGGL((k_bmigrate<3, false>), grid, block, 0, s, d, colour);
+                    hipLaunchKernelGGL((k_bmigrate_wave<3, false>), wgrid, wblock, 0, s, d, colour);
+                }
             } else {
-                if (h->poly) hipLaunchKernelGGL((k_bmigrate<2, true>), grid, block, 0, s, d, colour);
-                else hipLaunchKernelGGL((k_bmigrate<2, false>), grid, block, 0, s, d, colour);
+                if (h->poly) {
+                    hipLaunchKernelGGL((k_bmigrate<2, true>), grid, block, 0, s, d, colour);
+                    hipLaunchKernelGGL((k_bmigrate_wave<2, true>), wgrid, wblock, 0, s, d, colour);
+                } else {
+                    hipLaunchKernelGGL((k_bmigrate<2, false>), grid, block, 0, s, d, colour);
+                    hipLaunchKernelGGL((k_bmigrate_wave<2, false>), wgrid, wblock, 0, s, d, colour);
+                }
             }
         }
     }
@@ -559,12 +590,13 @@ srm_status srm_batch_init(int32_t count, const srm_params *params, const double 
     if (!e) e = balloc(h, &d.rve_of_cell, (size_t)ncells);
     if (!e) e = balloc(h, &d.cell, (size_t)ntotal);
     if (!e) e = balloc(h, &d.slot, (size_t)ntotal);
+    if (!e) e = balloc(h, &d.tmpid, (size_t)ntotal);
     if (!e) e = balloc(h, &d.counts, (size_t)ncells);
     if (!e) e = balloc(h, &d.start, (size_t)ncells + 1);
     if (!e) e = balloc(h, &d.partials, (size_t)(ncells / 2048 + 2));
     if (!e) e = balloc(h, &d.acc, (size_t)ntotal);
     if (!e) e = balloc(h, &d.failed, (size_t)ntotal + 1);
-    if (!e) e = balloc(h, &d.prefix, (size_t)16 * (count + 1));
+    if (!e) e = balloc(h, &d.prefix, (size_t)32 * (count + 1));
     if (!e) e = balloc(h, &d.remaining, 1);
     if (e) return bail(bfail(SRM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
     if (hipHostMalloc((void **)&h->hrem, sizeof(int32_t), hipHostMallocDefault) != hipSuccess)

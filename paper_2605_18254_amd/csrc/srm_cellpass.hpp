@@ -117,4 +117,241 @@ __device__ __forceinline__ bool check_ball_one(const PassArgs &a, int32_t p)
     return ball_hits<DIM, POLY, true>(a, lo, hi, p, x, y, z, Ri);
 }
 
+// ---- one wavefront per cell ------------------------------------------------
+//
+// For crowded cells (polydisperse boxes put tens of particles in a cell,
+// whose edge follows the largest radius) the whole 64-lane wavefront of a
+// 64-thread workgroup runs Algorithm 3 for one cell:
+//  A. the cell's particles go to LDS and each gets a near list: stencil
+//     candidates outside the cell within R_i + R_j + 2 c_m of it (they do
+//     not move in this colour phase, and a trial lies within c_m of the old
+//     position), and the cell's other particles within R_i + R_j + 3 c_m
+//     (each moves at most c_m before i's turn; the extra c_m is slack for
+//     rounding).  Lanes split the candidates.
+//  B. particles in ascending id order: the lanes split (trial, near entry)
+//     pairs of a group of consecutive trials, reading the cell's particles
+//     at their current LDS positions, and the lowest collision-free trial of
+//     the group wins -- the first free trial of the sequential rule, since
+//     no trial of one particle changes what another trial of it sees.
+// A particle whose near list overflows tests its trials one at a time
+// against the whole stencil; a cell with more than kWaveOwn particles runs
+// on one lane with the global-memory routine above.
+constexpr int kWaveOwn = 96;
+constexpr int kWaveNear = 32;
+constexpr int kWaveOccupancy = 3;  // mean particles per cell that selects this path
+
+struct WaveOwn {
+    double x, y, z, r;
+};
+
+struct WaveLds {
+    WaveOwn own[kWaveOwn];
+    int32_t nn[kWaveOwn];
+    int32_t near[kWaveOwn * kWaveNear];  // slot q >= 0, or -(k + 1) for own particle k
+};
+
+template <int DIM>
+__device__ __forceinline__ double wave_q(const Grid &g, double ax, double ay, double az, double bx,
+                                         double by, double bz)
+{
+    const double dx = min_image(ax - bx, g.box[0], g.half[0]);
+    const double dy = min_image(ay - by, g.box[1], g.half[1]);
+    double qq = dx * dx + dy * dy;
+    if (DIM == 3) {
+        const double dz = min_image(az - bz, g.box[2], g.half[2]);
+        qq = qq + dz * dz;
+    }
+    return qq;
+}
+
+// Trial l of the particle with id `id` at (ox, oy, oz): Algorithm 3's
+// wrapped position.
+template <int DIM>
+__device__ __forceinline__ void wave_trial(const PassArgs &a, uint32_t id, int32_t l, double ox,
+                                           double oy, double oz, double &yx, double &yy,
+                                           double &yz)
+{
+    Draw d = a.draw;
+    d.word = a.draw.word | ((uint32_t)l << 8);
+    double v[3];
+    unit_vector<DIM>(d, id, 0, a.c_m, v);
+    yx = wrap_coord(ox + v[0], a.g.box[0]);
+    yy = wrap_coord(oy + v[1], a.g.box[1]);
+    yz = (DIM == 3) ? wrap_coord(oz + v[2], a.g.box[2]) : 0.0;
+}
+
+// Exact Algorithm 5 predicate of a trial (radius Ri) against one candidate,
+// evaluated as in ball_hits: q = (dx*dx + dy*dy) + dz*dz <= (Ri + Rc)^2.
+template <int DIM, bool POLY>
+__device__ __forceinline__ bool wave_hit(const PassArgs &a, double yx, double yy, double yz,
+                                         double Ri, double cx, double cy, double cz, double Rc)
+{
+    const double dx = min_image(yx - cx, a.g.box[0], a.g.half[0]);
+    const double dy = min_image(yy - cy, a.g.box[1], a.g.half[1]);
+    double qq = dx * dx + dy * dy;
+    if (DIM == 3) {
+        const double dz = min_image(yz - cz, a.g.box[2], a.g.half[2]);
+        qq = qq + dz * dz;
+    }
+    double sig2;
+    if (POLY) {
+        const double sig = Ri + Rc;
+        sig2 = sig * sig;
+    } else {
+        sig2 = a.sig2_mono;
+    }
+    return qq <= sig2;
+}
+
+// Near-list entry `ref` against a trial of own particle k.
+template <int DIM, bool POLY>
+__device__ __forceinline__ bool wave_ref_hit(const PassArgs &a, const WaveLds &L, int32_t ref,
+                                             double yx, double yy, double yz, double Ri)
+{
+    if (ref < 0) {
+        const WaveOwn o = L.own[-ref - 1];
+        return wave_hit<DIM, POLY>(a, yx, yy, yz, Ri, o.x, o.y, o.z, o.r);
+    }
+    return wave_hit<DIM, POLY>(a, yx, yy, yz, Ri, a.buf.x[0][ref], a.buf.x[1][ref],
+                               (DIM == 3) ? a.buf.x[2][ref] : 0.0,
+                               POLY ? a.s * a.buf.rho[ref] : a.s);
+}
+
+// Must be called by all 64 threads of a 64-thread workgroup, uniformly.
+template <int DIM, bool POLY>
+__device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int32_t cz,
+                                  WaveLds &L)
+{
+    const int lane = threadIdx.x;
+    const int32_t c = cx + a.g.na[0] * (cy + a.g.na[1] * cz);
+    const int32_t beg = a.start[c], end = a.start[c + 1];
+    const int32_t cnt = end - beg;
+    if (cnt == 0) return;
+    if (cnt > kWaveOwn) {
+        if (lane == 0) migrate_cell_global<DIM, POLY>(a, cx, cy, cz);
+        return;
+    }
+    const double *__restrict__ X = a.buf.x[0];
+    const double *__restrict__ Y = a.buf.x[1];
+    const double *__restrict__ Z = a.buf.x[2];
+    int32_t lo[Rows<DIM>::kRanges], hi[Rows<DIM>::kRanges];
+    stencil_slices<DIM>(a.g, a.start, cx, cy, cz, lo, hi);
+    for (int32_t k = lane; k < cnt; k += 64) {
+        WaveOwn o;
+        o.x = X[beg + k];
+        o.y = Y[beg + k];
+        o.z = (DIM == 3) ? Z[beg + k] : 0.0;
+        o.r = POLY ? a.s * a.buf.rho[beg + k] : a.s;
+        L.own[k] = o;
+        L.nn[k] = 0;
+    }
+    __syncthreads();
+    // A. near lists
+#pragma unroll
+    for (int r = 0; r < Rows<DIM>::kRanges; ++r) {
+        for (int32_t q = lo[r] + lane; q < hi[r]; q += 64) {
+            if (q >= beg && q < end) continue;
+            const double qx = X[q], qy = Y[q], qz = (DIM == 3) ? Z[q] : 0.0;
+            const double Rq = POLY ? a.s * a.buf.rho[q] : a.s;
+            for (int32_t k = 0; k < cnt; ++k) {
+                const WaveOwn o = L.own[k];
+                const double reach = (o.r + Rq) + 2.0 * a.c_m;
+                if (wave_q<DIM>(a.g, o.x, o.y, o.z, qx, qy, qz) <= reach * reach) {
+                    const int32_t slot = atomicAdd(&L.nn[k], 1);
+                    if (slot < kWaveNear) L.near[k * kWaveNear + slot] = q;
+                }
+            }
+        }
+    }
+    for (int32_t j = lane; j < cnt; j += 64) {
+        const WaveOwn b = L.own[j];
+        for (int32_t k = 0; k < cnt; ++k) {
+            if (k == j) continue;
+            const WaveOwn o = L.own[k];
+            const double reach = (o.r + b.r) + 3.0 * a.c_m;
+            if (wave_q<DIM>(a.g, o.x, o.y, o.z, b.x, b.y, b.z) <= reach * reach) {
+                const int32_t slot = atomicAdd(&L.nn[k], 1);
+                if (slot < kWaveNear) L.near[k * kWaveNear + slot] = -(j + 1);
+            }
+        }
+    }
+    __syncthreads();
+    // B. the sequential part
+    for (int32_t k = 0; k < cnt; ++k) {
+        const int32_t p = beg + k;
+        const WaveOwn me = L.own[k];
+        const uint32_t id = (uint32_t)a.buf.id[p];
+        const int32_t m = L.nn[k];
+        int32_t code = 0;
+        double wx = 0.0, wy = 0.0, wz = 0.0;
+        if (m == 0) {
+            // nothing within reach: the first trial is free
+            wave_trial<DIM>(a, id, 1, me.x, me.y, me.z, wx, wy, wz);
+            code = (a.n_l >= 1) ? 1 : 0;
+        } else if (m <= kWaveNear) {
+            const int32_t G = 64 / m;
+            const int32_t g = lane / m, j = lane - g * m;
+            const unsigned long long seg = (m == 64) ? ~0ull : ((1ull << m) - 1ull);
+            for (int32_t l0 = 1; l0 <= a.n_l && code == 0; l0 += G) {
+                const int32_t l = l0 + g;
+                const bool active = g < G && l <= a.n_l;
+                double yx, yy, yz;
+                wave_trial<DIM>(a, id, active ? l : l0, me.x, me.y, me.z, yx, yy, yz);
+                const bool hit =
+                    active && wave_ref_hit<DIM, POLY>(a, L, L.near[k * kWaveNear + j], yx, yy, yz,
+                                                      me.r);
+                const unsigned long long hits = __ballot(hit);
+                int32_t win = -1;
+                for (int32_t gg = 0; gg < G && l0 + gg <= a.n_l; ++gg) {
+                    if (((hits >> (gg * m)) & seg) == 0) {
+                        win = gg;
+                        break;
+                    }
+                }
+                if (win >= 0) {
+                    code = l0 + win;
+                    wx = __shfl(yx, win * m, 64);
+                    wy = __shfl(yy, win * m, 64);
+                    wz = __shfl(yz, win * m, 64);
+                }
+            }
+        } else {
+            // near list overflowed: the whole stencil, one trial at a time
+            for (int32_t l = 1; l <= a.n_l && code == 0; ++l) {
+                double yx, yy, yz;
+                wave_trial<DIM>(a, id, l, me.x, me.y, me.z, yx, yy, yz);
+                bool hit = false;
+#pragma unroll
+                for (int r = 0; r < Rows<DIM>::kRanges; ++r) {
+                    for (int32_t q = lo[r] + lane; q < hi[r]; q += 64) {
+                        if (q >= beg && q < end) continue;
+                        hit = hit || wave_ref_hit<DIM, POLY>(a, L, q, yx, yy, yz, me.r);
+                    }
+                }
+                for (int32_t j = lane; j < cnt; j += 64)
+                    if (j != k) hit = hit || wave_ref_hit<DIM, POLY>(a, L, -(j + 1), yx, yy, yz, me.r);
+                if (__ballot(hit) == 0) {
+                    code = l;
+                    wx = yx;
+                    wy = yy;
+                    wz = yz;
+                }
+            }
+        }
+        if (lane == 0) {
+            if (code) {
+                L.own[k].x = wx;
+                L.own[k].y = wy;
+                L.own[k].z = wz;
+                a.buf.x[0][p] = wx;
+                a.buf.x[1][p] = wy;
+                if (DIM == 3) a.buf.x[2][p] = wz;
+            }
+            a.acc[p] = (uint8_t)code;
+            if (code == 0) a.failed[1 + atomicAdd(&a.failed[0], 1)] = p;
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace srm

@@ -173,6 +173,20 @@ def test_polydisperse_run_bitexact(srm, oracle_lib):
     g.close()
 
 
+@pytest.mark.parametrize("dim,n,seed,f,sigma", [(3, 2500, 75, 0.5, 0.2), (2, 3000, 74, 0.5, 0.5)])
+def test_crowded_cells_bitexact(srm, oracle_lib, dim, n, seed, f, sigma):
+    """Wide radius spreads make cells crowded (tens of particles a cell, a
+    4x4x4 grid in 3D at the end), which moves migration to one wavefront per
+    cell; every sweep still equals the oracle."""
+    w = _mk(dim, n, seed, f, polydisperse_sigma=sigma)
+    o, g, sweeps = _sweep_parity(srm, oracle_lib, w, 1000, every=3)
+    assert o.s == w.s_target
+    grid = g.grid(w.s_target)[:dim]
+    assert n >= 8 * int(np.prod(grid)), grid
+    _say(f"crowded {dim}D: {sweeps} sweeps, final grid {grid}")
+    g.close()
+
+
 def test_2d_polydisperse_fast_swell_with_shakes(srm, oracle_lib):
     """Large swelling steps and few trials: sweeps shake, and the shake
     branch must match too."""
