@@ -26,9 +26,54 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Vector ALU issue rate of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz.
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Algorithmic HBM bytes per particle update (3D spheres, FP64 SoA, int32 ids).
-MIGRATE_BYTES = 24 + 4 + 24 + 1 + 4   # own position, id, new position, accept code, cell range
+# Algorithmic HBM bytes of one migration colour phase (3D spheres, FP64 SoA,
+# int32 ids): the 3^3 stencils of one colour's cells cover the whole box, so
+# a phase reads every particle's position and id once and every cell range,
+# and writes its own particles' positions and accept codes.
+PHASE_READ_PER_PARTICLE = 24 + 4
+PHASE_READ_PER_CELL = 4
+PHASE_WRITE_PER_OWN = 24 + 1
 BIN_BYTES = (24 + 4 + 4 + 4) + (24 + 4 + 4 + 4 + 4 + 24 + 4) + 4  # count pass + scatter + fix-up
+
+
+# Sources of the migration kernels: HBM traffic recorded from counters is
+# reported only while these are unchanged.
+KERNEL_SOURCES = ["paper_2605_18254_amd/csrc/k_migrate.hip",
+                  "paper_2605_18254_amd/csrc/srm_cellpass.hpp",
+                  "paper_2605_18254_amd/csrc/srm_device.hpp",
+                  "paper_2605_18254_amd/csrc/srm_internal.hpp"]
+TRAFFIC_FILE = "profiles/migrate_tile_spheres3d_n1e7.md"
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when the
+    summary is missing, covers another kernel, or the sources changed."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].strip().split(": ", 1)
+                rec[k.strip("`")] = v.strip().strip("`")
+    try:
+        if rec.get("kernel") != kernel or rec.get("kernel_sources_sha256") != kernel_sources_sha256():
+            return None
+        return {"bytes_per_launch": float(rec["fetch_bytes_per_launch"]) +
+                float(rec["write_bytes_per_launch"]), "source": TRAFFIC_FILE}
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -44,6 +89,9 @@ def parse():
                     help="skip the batched-ensemble and gradient measurements")
     ap.add_argument("--batch-sweeps", type=int, default=400,
                     help="sweep budget of every RVE of the batched ensemble")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="copy this many MiB device to device before the sweeps (a plain copy "
+                         "kernel of known size, to calibrate HBM byte counters)")
     return ap.parse_args()
 
 
@@ -234,6 +282,12 @@ def main():
     import srm_inputs
 
     torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        a = torch.empty(args.copy_probe_mib << 17, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     w = srm_inputs.make("spheres3d", n=args.n)
     g = srm.SRM.from_workload(w, device=True)
     for _ in range(args.warmup):
@@ -242,8 +296,15 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     passes = shakes = 0
-    for _ in range(args.steps):
+    phase_bytes = 0  # algorithmic bytes of all timed colour phases
+    for step in range(args.steps):
         info = g.sweep()
+        npass = info["passes_main"] + info["passes_shake"]
+        ncell = info["grid"][0] * info["grid"][1] * info["grid"][2]
+        phase_bytes += npass * (8 * (PHASE_READ_PER_PARTICLE * w.n + PHASE_READ_PER_CELL * ncell)
+                                + PHASE_WRITE_PER_OWN * w.n)
+        if step % 25 == 24:
+            _say(f"sweep {step + 1}/{args.steps}")
         passes += info["passes_main"] + info["passes_shake"]
         shakes += 0 if info["committed"] else 1
     torch.cuda.synchronize()
@@ -257,9 +318,14 @@ def main():
     # dominant kernel: the migration colour phases
     mig_ms = prof["ms_migrate"]
     launches = max(prof["launches_migrate"], 1)
-    avg_launch_s = mig_ms / 1e3 / launches
+    # the colour phases' main kernel alone (the tiled kernel on this workload)
+    avg_launch_s = prof["ms_migrate_main"] / 1e3 / launches
+    main_name = {1: "k_migrate_tile<3,false>", 2: "k_migrate_wave<3,false>",
+                 4: "k_migrate_ball<3,false>"}.get(prof["main_kernels"], "mixed")
+    traffic = recorded_traffic(main_name)
     upd_per_launch = updates / launches
-    achieved_gbs = MIGRATE_BYTES * upd_per_launch / avg_launch_s / 1e9
+    bytes_per_launch = phase_bytes / launches
+    achieved_gbs = bytes_per_launch / avg_launch_s / 1e9
     out = {
         "metric": "particle-updates/sec per SRM sweep (N=1e7 3D)",
         "value": value,
@@ -278,15 +344,17 @@ def main():
                    "passes": passes, "shakes": shakes, "final_fraction": final["fraction"],
                    "final_sweep": final["sweep"], "grid": list(final["grid"])},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_migrate_tile<3,false> + k_migrate_overflow<3,false> (one colour phase)",
-                     "avg_launch_ms": avg_launch_s * 1e3,
-                     "bytes_per_update": MIGRATE_BYTES},
+                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
+                     "traffic": traffic["bytes_per_launch"] if traffic else None,
+                     "kernel": main_name, "avg_launch_ms": avg_launch_s * 1e3,
+                     "launches": launches, "alg_bytes_per_launch": bytes_per_launch,
+                     "updates_per_launch": upd_per_launch,
+                     "traffic_source": traffic["source"] if traffic else None},
         "kernel_ms": {"bin": prof["ms_bin"], "migrate": mig_ms, "check": prof["ms_check"],
                       "wall": dt * 1e3},
-        "hbm_sweep": {"bytes_per_update": MIGRATE_BYTES + BIN_BYTES,
-                      "achieved_gbs": (MIGRATE_BYTES + BIN_BYTES) * updates / dt / 1e9,
-                      "frac": (MIGRATE_BYTES + BIN_BYTES) * updates / dt / 1e9 / HBM_PEAK_GBS},
+        "hbm_sweep": {"alg_bytes": phase_bytes + BIN_BYTES * w.n * passes,
+                      "achieved_gbs": (phase_bytes + BIN_BYTES * w.n * passes) / dt / 1e9,
+                      "frac": (phase_bytes + BIN_BYTES * w.n * passes) / dt / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_extras:
         out["extras"] = {"batched": batched_extra(args.batch_sweeps),

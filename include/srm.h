@@ -260,7 +260,15 @@ typedef struct {
     int64_t launches_migrate;  /* colour-phase launches */
     int64_t passes;            /* migration passes */
     int64_t checks;            /* global checks */
+    double ms_migrate_main;    /* the colour phases' main kernels alone (no overflow launch) */
+    int64_t main_kernels;      /* SRM_KERNEL_* bits of the main kernels that ran */
 } srm_profile;
+
+/* Main migration kernel of a colour phase (srm_profile.main_kernels). */
+#define SRM_KERNEL_TILE 1     /* LDS-tiled, four lanes per cell */
+#define SRM_KERNEL_WAVE 2     /* one wavefront per crowded cell */
+#define SRM_KERNEL_CELL 4     /* one thread per cell (small grids) */
+#define SRM_KERNEL_PLATELET 8 /* platelets, one thread per cell */
 
 /* Switch profiling on (1) or off (0); resets the accumulated profile. */
 srm_status srm_profile_enable(srm_ctx *ctx, int32_t on);

@@ -55,7 +55,8 @@ class SweepInfo(C.Structure):
 class Profile(C.Structure):
     _fields_ = [("ms_bin", C.c_double), ("ms_migrate", C.c_double), ("ms_check", C.c_double),
                 ("bins", C.c_int64), ("launches_migrate", C.c_int64), ("passes", C.c_int64),
-                ("checks", C.c_int64)]
+                ("checks", C.c_int64), ("ms_migrate_main", C.c_double),
+                ("main_kernels", C.c_int64)]
 
 
 class RunInfo(C.Structure):

@@ -711,11 +711,16 @@ bool wave_cells(int dim, const Grid &g, int32_t n)
 }
 
 hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int colour,
-                          hipStream_t stream, bool *launched)
+                          hipStream_t stream, bool *launched, hipEvent_t after_main, int *which)
 {
     ColourLattice L;
     *launched = false;
     if (!colour_lattice(dim, a.g, colour, L)) return hipSuccess;
+    auto main_done = [&](int kind) {
+        if (after_main) (void)hipEventRecord(after_main, stream);
+        if (which) *which = kind;
+        *launched = true;
+    };
     if (shape != SRM_PLATELET && wave_cells(dim, a.g, a.n)) {
         const dim3 grid(L.count), block(64);
         if (dim == 3) {
@@ -725,7 +730,7 @@ hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int 
             if (poly) hipLaunchKernelGGL((k_migrate_wave<2, true>), grid, block, 0, stream, a, L);
             else hipLaunchKernelGGL((k_migrate_wave<2, false>), grid, block, 0, stream, a, L);
         }
-        *launched = true;
+        main_done(SRM_KERNEL_WAVE);
         return hipGetLastError();
     }
     if (shape != SRM_PLATELET && a.ovf && tile_ok(dim, a.g)) {
@@ -746,37 +751,38 @@ hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int 
             const dim3 grid(8 * T.per_xcd), block(256);
             const dim3 ogrid(T.tiles < 512 ? T.tiles : 512), oblock(64);
             if (dim == 3) {
-                if (poly) {
-                    hipLaunchKernelGGL((k_migrate_tile<3, true>), grid, block, 0, stream, a, T);
-                    hipLaunchKernelGGL((k_migrate_overflow<3, true>), ogrid, oblock, 0, stream, a, T);
-                } else {
-                    hipLaunchKernelGGL((k_migrate_tile<3, false>), grid, block, 0, stream, a, T);
-                    hipLaunchKernelGGL((k_migrate_overflow<3, false>), ogrid, oblock, 0, stream, a, T);
-                }
+                if (poly) hipLaunchKernelGGL((k_migrate_tile<3, true>), grid, block, 0, stream, a, T);
+                else hipLaunchKernelGGL((k_migrate_tile<3, false>), grid, block, 0, stream, a, T);
             } else {
-                if (poly) {
-                    hipLaunchKernelGGL((k_migrate_tile<2, true>), grid, block, 0, stream, a, T);
-                    hipLaunchKernelGGL((k_migrate_overflow<2, true>), ogrid, oblock, 0, stream, a, T);
-                } else {
-                    hipLaunchKernelGGL((k_migrate_tile<2, false>), grid, block, 0, stream, a, T);
-                    hipLaunchKernelGGL((k_migrate_overflow<2, false>), ogrid, oblock, 0, stream, a, T);
-                }
+                if (poly) hipLaunchKernelGGL((k_migrate_tile<2, true>), grid, block, 0, stream, a, T);
+                else hipLaunchKernelGGL((k_migrate_tile<2, false>), grid, block, 0, stream, a, T);
             }
-            *launched = true;
+            main_done(SRM_KERNEL_TILE);
+            // tiles whose neighbourhood did not fit LDS
+            if (dim == 3) {
+                if (poly) hipLaunchKernelGGL((k_migrate_overflow<3, true>), ogrid, oblock, 0, stream, a, T);
+                else hipLaunchKernelGGL((k_migrate_overflow<3, false>), ogrid, oblock, 0, stream, a, T);
+            } else {
+                if (poly) hipLaunchKernelGGL((k_migrate_overflow<2, true>), ogrid, oblock, 0, stream, a, T);
+                else hipLaunchKernelGGL((k_migrate_overflow<2, false>), ogrid, oblock, 0, stream, a, T);
+            }
             return hipGetLastError();
         }
     }
     const dim3 grid(blocks_for(L.count)), block(kBlock);
     if (shape == SRM_PLATELET) {
         hipLaunchKernelGGL(k_migrate_platelet, grid, block, 0, stream, a, L);
-    } else if (dim == 3) {
-        if (poly) hipLaunchKernelGGL((k_migrate_ball<3, true>), grid, block, 0, stream, a, L);
-        else hipLaunchKernelGGL((k_migrate_ball<3, false>), grid, block, 0, stream, a, L);
+        main_done(SRM_KERNEL_PLATELET);
     } else {
-        if (poly) hipLaunchKernelGGL((k_migrate_ball<2, true>), grid, block, 0, stream, a, L);
-        else hipLaunchKernelGGL((k_migrate_ball<2, false>), grid, block, 0, stream, a, L);
+        if (dim == 3) {
+            if (poly) hipLaunchKernelGGL((k_migrate_ball<3, true>), grid, block, 0, stream, a, L);
+            else hipLaunchKernelGGL((k_migrate_ball<3, false>), grid, block, 0, stream, a, L);
+        } else {
+            if (poly) hipLaunchKernelGGL((k_migrate_ball<2, true>), grid, block, 0, stream, a, L);
+            else hipLaunchKernelGGL((k_migrate_ball<2, false>), grid, block, 0, stream, a, L);
+        }
+        main_done(SRM_KERNEL_CELL);
     }
-    *launched = true;
     return hipGetLastError();
 }
 

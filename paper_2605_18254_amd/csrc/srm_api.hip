@@ -77,7 +77,7 @@ struct srm_ctx {
     srm_profile prof{};
     std::vector<hipEvent_t> ev_free;
     struct Pending {
-        int kind;  // 0 bin, 1 migrate, 2 check
+        int kind;  // 0 bin, 1 migrate (colour phase), 2 check, 3 main migration kernel
         hipEvent_t a, b;
     };
     std::vector<Pending> pending;
@@ -137,6 +137,7 @@ struct srm_ctx {
             if (hipEventElapsedTime(&ms, p_.a, p_.b) == hipSuccess) {
                 if (p_.kind == 0) prof.ms_bin += ms;
                 else if (p_.kind == 1) prof.ms_migrate += ms;
+                else if (p_.kind == 3) prof.ms_migrate_main += ms;
                 else prof.ms_check += ms;
             }
             release(p_.a);
@@ -230,12 +231,24 @@ srm_status run_pass(srm_ctx *c, const PBuf &b, const Grid &g, double s, int kind
     hipEvent_t e0 = c->mark();
     for (int colour = 0; colour < (1 << c->dim); ++colour) {
         bool launched = false;
-        HIP_TRY(migrate_colour(c->dim, c->p.shape, c->poly, a, colour, c->stream, &launched));
+        int which = 0;
+        // m0 .. m1 brackets the colour phase's main kernel alone
+        hipEvent_t m0 = c->mark();
+        hipEvent_t m1 = c->prof_on ? c->event() : nullptr;
+        HIP_TRY(migrate_colour(c->dim, c->p.shape, c->poly, a, colour, c->stream, &launched, m1,
+                               &which));
         if (launched) {
             hipEvent_t e1 = c->mark();
             c->span(1, e0, e1);
+            c->span(3, m0, m1);
             e0 = e1 ? c->mark() : nullptr;
-            if (c->prof_on) c->prof.launches_migrate += 1;
+            if (c->prof_on) {
+                c->prof.launches_migrate += 1;
+                c->prof.main_kernels |= which;
+            }
+        } else {
+            c->release(m0);
+            c->release(m1);
         }
     }
     if (e0) c->release(e0);

@@ -84,8 +84,12 @@ struct PassArgs {
 
 // One colour phase of a migration pass (Algorithm 3 over the cells whose
 // parity vector is `colour`); *launched is false for an empty phase.
+// One colour phase of Algorithm 3.  If `after_main` is given it is recorded
+// right after the phase's main kernel (before any overflow launch), and
+// *which gets that kernel's kind (SRM_KERNEL_* bits of srm_profile).
 hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int colour,
-                          hipStream_t stream, bool *launched);
+                          hipStream_t stream, bool *launched, hipEvent_t after_main = nullptr,
+                          int *which = nullptr);
 // Global check (Algorithm 6) restricted to particles with accept code 0
 // (or every particle when check_all), result into cnt.
 hipError_t check_overlaps(int dim, int shape, bool poly, const PassArgs &a, bool check_all,
