@@ -186,6 +186,35 @@ def batched_extra(max_sweeps):
     }
 
 
+def platelet_extra(max_sweeps):
+    """Thin circular platelets (thickness D/100), N = 2e5, target volume
+    fraction 0.02, exact disk-disk test, migration of centre and normal:
+    one run from isotropic normals, one from normals within 15 degrees of a
+    common axis."""
+    import torch
+
+    import paper_2605_18254_amd as srm
+    import srm_inputs
+
+    out = {}
+    for tag, cap in (("isotropic", None), ("cap15", 15.0)):
+        w = srm_inputs.make("platelets", cap_deg=cap)
+        g = srm.SRM.from_workload(w, device=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = g.run(max_sweeps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        overlaps = len(g.pairs(0.0))
+        g.close()
+        out[tag] = {"converged": st == 0, "sweeps": info["sweeps"], "passes": info["passes"],
+                    "s": dt, "updates_per_s": info["updates"] / dt,
+                    "fraction": info["fraction"], "overlapping_pairs": overlaps}
+        _say(f"platelets {tag}: {out[tag]}")
+    out["workload"] = ("platelets N=2e5, thickness D/100, f_target=0.02, seed 2, c_w=0.01, "
+                       "c_m=0.1*s_target, c_n=c_m/a_t, N_k=N_l=8")
+    return out
+
 def grad_extra(steps, steer_steps):
     """Soft g(r) (64 Gaussian bins up to 5r) + overlap energy, forward and
     hand-written backward, on N = 2e5 spheres grown by SRM to f = 0.30; then
@@ -357,7 +386,8 @@ def main():
                       "frac": (phase_bytes + BIN_BYTES * w.n * passes) / dt / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_extras:
-        out["extras"] = {"batched": batched_extra(args.batch_sweeps),
+        out["extras"] = {"platelets": platelet_extra(3000),
+                         "batched": batched_extra(args.batch_sweeps),
                          "gradient": grad_extra(20, 10)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_fraction)
