@@ -26,10 +26,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Vector ALU issue rate of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz.
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Algorithmic HBM bytes of one migration colour phase (3D spheres, FP64 SoA,
-# int32 ids): the 3^3 stencils of one colour's cells cover the whole box, so
-# a phase reads every particle's position and id once and every cell range,
-# and writes its own particles' positions and accept codes.
+# Algorithmic HBM bytes per particle update of the migration kernel (3D
+# spheres, FP64 SoA, int32 ids): read the particle's position and id, write
+# its new position.
+ALG_BYTES_PER_UPDATE = 24 + 4 + 24
+# Floor of one colour phase's traffic: the 3^3 stencils of one colour's
+# cells cover the whole box, so a phase reads every particle's position and
+# id once and every cell range, and writes its own particles' positions and
+# accept codes.
 PHASE_READ_PER_PARTICLE = 24 + 4
 PHASE_READ_PER_CELL = 4
 PHASE_WRITE_PER_OWN = 24 + 1
@@ -353,8 +357,9 @@ def main():
                  4: "k_migrate_ball<3,false>"}.get(prof["main_kernels"], "mixed")
     traffic = recorded_traffic(main_name)
     upd_per_launch = updates / launches
-    bytes_per_launch = phase_bytes / launches
+    bytes_per_launch = ALG_BYTES_PER_UPDATE * upd_per_launch
     achieved_gbs = bytes_per_launch / avg_launch_s / 1e9
+    floor_per_launch = phase_bytes / launches
     out = {
         "metric": "particle-updates/sec per SRM sweep (N=1e7 3D)",
         "value": value,
@@ -377,7 +382,10 @@ def main():
                      "traffic": traffic["bytes_per_launch"] if traffic else None,
                      "kernel": main_name, "avg_launch_ms": avg_launch_s * 1e3,
                      "launches": launches, "alg_bytes_per_launch": bytes_per_launch,
+                     "alg_bytes_per_update": ALG_BYTES_PER_UPDATE,
                      "updates_per_launch": upd_per_launch,
+                     "phase_floor_bytes_per_launch": floor_per_launch,
+                     "phase_floor_gbs": floor_per_launch / avg_launch_s / 1e9,
                      "traffic_source": traffic["source"] if traffic else None},
         "kernel_ms": {"bin": prof["ms_bin"], "migrate": mig_ms, "check": prof["ms_check"],
                       "wall": dt * 1e3},
