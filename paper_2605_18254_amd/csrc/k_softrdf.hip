@@ -14,7 +14,14 @@
 // Forward: one thread per particle accumulates its pairs with larger ids in
 // registers (FP64); blocks reduce in a fixed tree order and a final kernel
 // sums the block partials in block order, so the result is the same on
-// every run.  Backward: one thread per particle gathers dL/dr_ij * u_ij over
+// every run.
+//
+// Per pair the 64 Gaussians come from three exponentials: with u_b =
+// (r - c_b)/h and c_{b+1} - c_b = h, K_{b+1}/K_b = exp(u_b - 1/2) and
+// K_{b-1}/K_b = exp(-u_b - 1/2), and each ratio shrinks by e^-1 per step.
+// Starting at the bin nearest r (|u| <= 1/2) both chains only decrease, so
+// the products lose about one ulp per step (relative) and reach zero where
+// the exponential itself underflows.  Backward: one thread per particle gathers dL/dr_ij * u_ij over
 // all its neighbours -- pairs are recomputed, not stored -- and writes only
 // its own gradient (no atomics).
 #include "srm_internal.hpp"
@@ -24,6 +31,7 @@ namespace {
 
 constexpr int kBlock = 128;
 constexpr int kMaxBins = 64;
+constexpr double kInvE = 0.36787944117144233;  // e^-1 rounded to binary64
 
 struct SoftArgs {
     PBuf buf;              // cell-sorted positions, ids, radii (in rho)
@@ -98,11 +106,28 @@ __global__ void __launch_bounds__(kBlock) k_soft_fwd(SoftArgs a, double *__restr
                 if (r >= a.cut) continue;
                 double dw;
                 const double w = taper(r, a.r_c, a.h, &dw);
+                int32_t b0 = (int32_t)(r / a.h);
+                b0 = b0 < a.nbins ? b0 : a.nbins - 1;
+                const double u0 = (r - (b0 + 0.5) * D) / a.h;
+                const double k0 = c0 * exp(-0.5 * u0 * u0) * w;
+                double ku = k0, ru = exp(u0 - 0.5);
 #pragma unroll
                 for (int b = 0; b < kMaxBins; ++b) {
-                    if (b < a.nbins) {
-                        const double u = (r - (b + 0.5) * D) / a.h;
-                        acc[b] += c0 * exp(-0.5 * u * u) * w;
+                    if (b < a.nbins && b >= b0) {
+                        if (b > b0) {
+                            ku *= ru;
+                            ru *= kInvE;
+                        }
+                        acc[b] += ku;
+                    }
+                }
+                double kd = k0, rd = exp(-u0 - 0.5);
+#pragma unroll
+                for (int b = kMaxBins - 1; b >= 0; --b) {
+                    if (b < b0) {
+                        kd *= rd;
+                        rd *= kInvE;
+                        acc[b] += kd;
                     }
                 }
             }
@@ -181,11 +206,26 @@ __global__ void __launch_bounds__(kBlock) k_soft_bwd(SoftArgs a, const double *_
             if (r < a.cut) {
                 double dw;
                 const double w = taper(r, a.r_c, a.h, &dw);
-                for (int b = 0; b < a.nbins; ++b) {
-                    const double u = (r - (b + 0.5) * D) / a.h;
-                    const double k = c0 * exp(-0.5 * u * u);
-                    const double dk = k * (-u / a.h);
-                    dLdr += coef[b] * (dk * w + k * dw);
+                // d/dr [K_b w] = K_b (w (-u_b / h) + dw), K_b by the chains above
+                int32_t b0 = (int32_t)(r / a.h);
+                b0 = b0 < a.nbins ? b0 : a.nbins - 1;
+                const double u0 = (r - (b0 + 0.5) * D) / a.h;
+                const double k0 = c0 * exp(-0.5 * u0 * u0);
+                const double inv_h = 1.0 / a.h;
+                dLdr += coef[b0] * (k0 * (w * (-u0 * inv_h) + dw));
+                double ku = k0, ru = exp(u0 - 0.5), uu = u0;
+                for (int32_t b = b0 + 1; b < a.nbins; ++b) {
+                    ku *= ru;
+                    ru *= kInvE;
+                    uu -= 1.0;
+                    dLdr += coef[b] * (ku * (w * (-uu * inv_h) + dw));
+                }
+                double kd = k0, rd = exp(-u0 - 0.5), ud = u0;
+                for (int32_t b = b0 - 1; b >= 0; --b) {
+                    kd *= rd;
+                    rd *= kInvE;
+                    ud += 1.0;
+                    dLdr += coef[b] * (kd * (w * (-ud * inv_h) + dw));
                 }
             }
             const double f = dLdr / r;
