@@ -587,6 +587,8 @@ __device__ __forceinline__ bool platelet_hits(const PassArgs &a, const int32_t *
     return false;
 }
 
+__device__ void migrate_platelet_cell(const PassArgs &a, int32_t cx, int32_t cy, int32_t cz);
+
 __global__ void __launch_bounds__(kBlock) k_migrate_platelet(PassArgs a, ColourLattice L)
 {
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -595,9 +597,86 @@ __global__ void __launch_bounds__(kBlock) k_migrate_platelet(PassArgs a, ColourL
     const int32_t r1 = t / L.h[0];
     const int32_t jy = r1 % L.h[1];
     const int32_t jz = r1 / L.h[1];
-    const int32_t cx = 2 * jx + L.off[0];
-    const int32_t cy = 2 * jy + L.off[1];
-    const int32_t cz = 2 * jz + L.off[2];
+    migrate_platelet_cell(a, 2 * jx + L.off[0], 2 * jy + L.off[1], 2 * jz + L.off[2]);
+}
+
+// Platelets on crowded grids: one 64-lane wavefront per colour cell, the
+// scheme of migrate_cell_wave.  A disk meets another only if their centres
+// are within a_i + a_j, so the near lists are built on centre distance
+// (+ 2 c_m for candidates outside the cell, + 3 c_m for cell mates) and the
+// lanes split (trial, near entry) pairs, each running the exact disk-disk
+// test with the lower id as disk 1.
+constexpr int kPlateOwn = 64;
+constexpr int kPlateNear = 32;
+
+struct PlateOwn {
+    double x, y, z, a, n0, n1, n2;
+    int32_t id, pad;
+};
+
+struct PlateLds {
+    PlateOwn own[kPlateOwn];
+    int32_t nn[kPlateOwn];
+    int32_t near[kPlateOwn * kPlateNear];  // slot q >= 0, or -(k + 1) for own particle k
+};
+
+// Trial l of a platelet: centre (stream 0, length c_m, wrapped) and normal
+// (stream 1: (n + c_n w) / |n + c_n w|).
+__device__ __forceinline__ void plate_trial(const PassArgs &a, const PlateOwn &me, int32_t l,
+                                            double y[3], double ny[3])
+{
+    Draw d = a.draw;
+    d.word = a.draw.word | ((uint32_t)l << 8);
+    double v[3], w[3];
+    unit_vector<3>(d, (uint32_t)me.id, 0, a.c_m, v);
+    y[0] = wrap_coord(me.x + v[0], a.g.box[0]);
+    y[1] = wrap_coord(me.y + v[1], a.g.box[1]);
+    y[2] = wrap_coord(me.z + v[2], a.g.box[2]);
+    unit_vector<3>(d, (uint32_t)me.id, 1, a.c_n, w);
+    const double m0 = me.n0 + w[0], m1 = me.n1 + w[1], m2 = me.n2 + w[2];
+    const double mm = m0 * m0 + m1 * m1 + m2 * m2;
+    const double inv = 1.0 / __builtin_sqrt(mm);
+    ny[0] = m0 * inv;
+    ny[1] = m1 * inv;
+    ny[2] = m2 * inv;
+}
+
+// The exact pair test of platelet_hits for one candidate.
+__device__ __forceinline__ bool plate_pair_hit(const PassArgs &a, int32_t self_id, const double y[3],
+                                               const double ny[3], double ai, double qx, double qy,
+                                               double qz, const double nq[3], double aj,
+                                               int32_t qid)
+{
+    if (self_id < qid) {
+        const double dx = min_image(qx - y[0], a.g.box[0], a.g.half[0]);
+        const double dy = min_image(qy - y[1], a.g.box[1], a.g.half[1]);
+        const double dz = min_image(qz - y[2], a.g.box[2], a.g.half[2]);
+        return disks_intersect(dx, dy, dz, ny, ai, nq, aj);
+    }
+    const double dx = min_image(y[0] - qx, a.g.box[0], a.g.half[0]);
+    const double dy = min_image(y[1] - qy, a.g.box[1], a.g.half[1]);
+    const double dz = min_image(y[2] - qz, a.g.box[2], a.g.half[2]);
+    return disks_intersect(dx, dy, dz, nq, aj, ny, ai);
+}
+
+__device__ __forceinline__ bool plate_ref_hit(const PassArgs &a, const PlateLds &L, int32_t ref,
+                                              int32_t self_id, const double y[3],
+                                              const double ny[3], double ai)
+{
+    if (ref < 0) {
+        const PlateOwn o = L.own[-ref - 1];
+        const double nq[3] = {o.n0, o.n1, o.n2};
+        return plate_pair_hit(a, self_id, y, ny, ai, o.x, o.y, o.z, nq, o.a, o.id);
+    }
+    const double nq[3] = {a.buf.nrm[0][ref], a.buf.nrm[1][ref], a.buf.nrm[2][ref]};
+    const double aj = a.buf.rho ? a.s * a.buf.rho[ref] : a.s;
+    return plate_pair_hit(a, self_id, y, ny, ai, a.buf.x[0][ref], a.buf.x[1][ref],
+                          a.buf.x[2][ref], nq, aj, a.buf.id[ref]);
+}
+
+// Algorithm 3 for the platelets of one cell (global-memory path, one thread).
+__device__ void migrate_platelet_cell(const PassArgs &a, int32_t cx, int32_t cy, int32_t cz)
+{
     const int32_t c = cx + a.g.na[0] * (cy + a.g.na[1] * cz);
     const int32_t beg = a.start[c], end = a.start[c + 1];
     if (beg == end) return;
@@ -638,6 +717,165 @@ __global__ void __launch_bounds__(kBlock) k_migrate_platelet(PassArgs a, ColourL
         }
         a.acc[p] = code;
         if (code == 0) a.failed[1 + atomicAdd(&a.failed[0], 1)] = p;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, ColourLattice L)
+{
+    __shared__ PlateLds S;
+    const int lane = threadIdx.x;
+    const int32_t t = blockIdx.x;
+    const int32_t jx = t % L.h[0];
+    const int32_t r1 = t / L.h[0];
+    const int32_t jy = r1 % L.h[1];
+    const int32_t jz = r1 / L.h[1];
+    const int32_t cx = 2 * jx + L.off[0];
+    const int32_t cy = 2 * jy + L.off[1];
+    const int32_t cz = 2 * jz + L.off[2];
+    const int32_t c = cx + a.g.na[0] * (cy + a.g.na[1] * cz);
+    const int32_t beg = a.start[c], end = a.start[c + 1];
+    const int32_t cnt = end - beg;
+    if (cnt == 0) return;
+    if (cnt > kPlateOwn) {
+        if (lane == 0) migrate_platelet_cell(a, cx, cy, cz);
+        return;
+    }
+    int32_t lo[Rows<3>::kRanges], hi[Rows<3>::kRanges];
+    stencil_slices<3>(a.g, a.start, cx, cy, cz, lo, hi);
+    for (int32_t k = lane; k < cnt; k += 64) {
+        const int32_t q = beg + k;
+        PlateOwn o;
+        o.x = a.buf.x[0][q];
+        o.y = a.buf.x[1][q];
+        o.z = a.buf.x[2][q];
+        o.a = a.buf.rho ? a.s * a.buf.rho[q] : a.s;
+        o.n0 = a.buf.nrm[0][q];
+        o.n1 = a.buf.nrm[1][q];
+        o.n2 = a.buf.nrm[2][q];
+        o.id = a.buf.id[q];
+        o.pad = 0;
+        S.own[k] = o;
+        S.nn[k] = 0;
+    }
+    __syncthreads();
+    // A. near lists on centre distance
+#pragma unroll
+    for (int r = 0; r < Rows<3>::kRanges; ++r) {
+        for (int32_t q = lo[r] + lane; q < hi[r]; q += 64) {
+            if (q >= beg && q < end) continue;
+            const double qx = a.buf.x[0][q], qy = a.buf.x[1][q], qz = a.buf.x[2][q];
+            const double aq = a.buf.rho ? a.s * a.buf.rho[q] : a.s;
+            for (int32_t k = 0; k < cnt; ++k) {
+                const PlateOwn o = S.own[k];
+                const double reach = (o.a + aq) + 2.0 * a.c_m;
+                const double dx = min_image(o.x - qx, a.g.box[0], a.g.half[0]);
+                const double dy = min_image(o.y - qy, a.g.box[1], a.g.half[1]);
+                const double dz = min_image(o.z - qz, a.g.box[2], a.g.half[2]);
+                if ((dx * dx + dy * dy) + dz * dz <= reach * reach) {
+                    const int32_t slot = atomicAdd(&S.nn[k], 1);
+                    if (slot < kPlateNear) S.near[k * kPlateNear + slot] = q;
+                }
+            }
+        }
+    }
+    for (int32_t j = lane; j < cnt; j += 64) {
+        const PlateOwn b = S.own[j];
+        for (int32_t k = 0; k < cnt; ++k) {
+            if (k == j) continue;
+            const PlateOwn o = S.own[k];
+            const double reach = (o.a + b.a) + 3.0 * a.c_m;
+            const double dx = min_image(o.x - b.x, a.g.box[0], a.g.half[0]);
+            const double dy = min_image(o.y - b.y, a.g.box[1], a.g.half[1]);
+            const double dz = min_image(o.z - b.z, a.g.box[2], a.g.half[2]);
+            if ((dx * dx + dy * dy) + dz * dz <= reach * reach) {
+                const int32_t slot = atomicAdd(&S.nn[k], 1);
+                if (slot < kPlateNear) S.near[k * kPlateNear + slot] = -(j + 1);
+            }
+        }
+    }
+    __syncthreads();
+    // B. the sequential part
+    for (int32_t k = 0; k < cnt; ++k) {
+        const int32_t p = beg + k;
+        const PlateOwn me = S.own[k];
+        const int32_t m = S.nn[k];
+        int32_t code = 0;
+        double w0 = 0.0, w1 = 0.0, w2 = 0.0, v0 = 0.0, v1 = 0.0, v2 = 0.0;
+        if (m <= kPlateNear) {
+            const int32_t mm = m > 0 ? m : 1;
+            const int32_t G = 64 / mm;
+            const int32_t g = lane / mm, j = lane - g * mm;
+            const unsigned long long seg = (mm == 64) ? ~0ull : ((1ull << mm) - 1ull);
+            for (int32_t l0 = 1; l0 <= a.n_l && code == 0; l0 += G) {
+                const int32_t l = l0 + g;
+                const bool active = g < G && l <= a.n_l;
+                double y[3], ny[3];
+                plate_trial(a, me, active ? l : l0, y, ny);
+                const bool hit = active && m > 0 &&
+                                 plate_ref_hit(a, S, S.near[k * kPlateNear + j], me.id, y, ny, me.a);
+                const unsigned long long hits = __ballot(hit);
+                int32_t win = -1;
+                for (int32_t gg = 0; gg < G && l0 + gg <= a.n_l; ++gg) {
+                    if (((hits >> (gg * mm)) & seg) == 0) {
+                        win = gg;
+                        break;
+                    }
+                }
+                if (win >= 0) {
+                    code = l0 + win;
+                    w0 = __shfl(y[0], win * mm, 64);
+                    w1 = __shfl(y[1], win * mm, 64);
+                    w2 = __shfl(y[2], win * mm, 64);
+                    v0 = __shfl(ny[0], win * mm, 64);
+                    v1 = __shfl(ny[1], win * mm, 64);
+                    v2 = __shfl(ny[2], win * mm, 64);
+                }
+            }
+        } else {
+            // near list overflowed: the whole stencil, one trial at a time
+            for (int32_t l = 1; l <= a.n_l && code == 0; ++l) {
+                double y[3], ny[3];
+                plate_trial(a, me, l, y, ny);
+                bool hit = false;
+#pragma unroll
+                for (int r = 0; r < Rows<3>::kRanges; ++r) {
+                    for (int32_t q = lo[r] + lane; q < hi[r]; q += 64) {
+                        if (q >= beg && q < end) continue;
+                        hit = hit || plate_ref_hit(a, S, q, me.id, y, ny, me.a);
+                    }
+                }
+                for (int32_t j = lane; j < cnt; j += 64)
+                    if (j != k) hit = hit || plate_ref_hit(a, S, -(j + 1), me.id, y, ny, me.a);
+                if (__ballot(hit) == 0) {
+                    code = l;
+                    w0 = y[0];
+                    w1 = y[1];
+                    w2 = y[2];
+                    v0 = ny[0];
+                    v1 = ny[1];
+                    v2 = ny[2];
+                }
+            }
+        }
+        if (lane == 0) {
+            if (code) {
+                S.own[k].x = w0;
+                S.own[k].y = w1;
+                S.own[k].z = w2;
+                S.own[k].n0 = v0;
+                S.own[k].n1 = v1;
+                S.own[k].n2 = v2;
+                a.buf.x[0][p] = w0;
+                a.buf.x[1][p] = w1;
+                a.buf.x[2][p] = w2;
+                a.buf.nrm[0][p] = v0;
+                a.buf.nrm[1][p] = v1;
+                a.buf.nrm[2][p] = v2;
+            }
+            a.acc[p] = (uint8_t)code;
+            if (code == 0) a.failed[1 + atomicAdd(&a.failed[0], 1)] = p;
+        }
+        __syncthreads();
     }
 }
 
@@ -771,8 +1009,13 @@ hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int 
     }
     const dim3 grid(blocks_for(L.count)), block(kBlock);
     if (shape == SRM_PLATELET) {
-        hipLaunchKernelGGL(k_migrate_platelet, grid, block, 0, stream, a, L);
-        main_done(SRM_KERNEL_PLATELET);
+        if (wave_cells(dim, a.g, a.n)) {
+            hipLaunchKernelGGL(k_migrate_platelet_wave, dim3(L.count), dim3(64), 0, stream, a, L);
+            main_done(SRM_KERNEL_PLATELET | SRM_KERNEL_WAVE);
+        } else {
+            hipLaunchKernelGGL(k_migrate_platelet, grid, block, 0, stream, a, L);
+            main_done(SRM_KERNEL_PLATELET);
+        }
     } else {
         if (dim == 3) {
             if (poly) hipLaunchKernelGGL((k_migrate_ball<3, true>), grid, block, 0, stream, a, L);
