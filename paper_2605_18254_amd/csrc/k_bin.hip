@@ -1,9 +1,10 @@
 // k_bin.hip -- Algorithm 2 (build cell list) as a counting sort on gfx950:
 // cell ids + per-cell counts, an exclusive prefix scan of the counts
-// (wavefront shuffles, LDS for the wave totals), a scatter into cell-sorted
-// SoA arrays, and a per-cell fix-up that restores ascending particle ids
-// inside each cell (the atomic slot order is not deterministic; the order
-// within a cell is part of the sequential processing order).
+// (wavefront shuffles, LDS for the wave totals), then placement into
+// cell-sorted SoA arrays with ascending particle ids inside each cell (the
+// atomic slot order is not deterministic; the order within a cell is part
+// of the sequential processing order): the ids are scattered in arrival
+// order, and each particle's rank among its cell's ids gives its slot.
 #include "srm_internal.hpp"
 
 namespace srm {
@@ -193,71 +194,9 @@ __global__ void __launch_bounds__(kBlock) k_scan_final(const int32_t *__restrict
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_scatter(PBuf src, PBuf dst, int32_t n, int dim,
-                                                    const int32_t *__restrict__ cell,
-                                                    const int32_t *__restrict__ slot,
-                                                    const int32_t *__restrict__ start)
-{
-    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int32_t d = start[cell[p]] + slot[p];
-    dst.x[0][d] = src.x[0][p];
-    dst.x[1][d] = src.x[1][p];
-    if (dim == 3) dst.x[2][d] = src.x[2][p];
-    dst.id[d] = src.id[p];
-    if (src.rho) dst.rho[d] = src.rho[p];
-    if (src.nrm[0]) {
-        dst.nrm[0][d] = src.nrm[0][p];
-        dst.nrm[1][d] = src.nrm[1][p];
-        dst.nrm[2][d] = src.nrm[2][p];
-    }
-}
-
-// Restore ascending ids within each cell (insertion sort of the cell's
-// slice; most slices are already ordered and are only read).
-__global__ void __launch_bounds__(kBlock) k_fixup(PBuf b, int dim, const int32_t *__restrict__ start,
-                                                  int32_t ncell)
-{
-    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    const int32_t beg = start[c], end = start[c + 1];
-    if (end - beg < 2) return;
-    bool sorted = true;
-    for (int32_t i = beg + 1; i < end; ++i) sorted = sorted && (b.id[i - 1] < b.id[i]);
-    if (sorted) return;
-    for (int32_t i = beg + 1; i < end; ++i) {
-        const int32_t key = b.id[i];
-        const double kx = b.x[0][i], ky = b.x[1][i], kz = (dim == 3) ? b.x[2][i] : 0.0;
-        const double kr = b.rho ? b.rho[i] : 0.0;
-        double kn0 = 0.0, kn1 = 0.0, kn2 = 0.0;
-        if (b.nrm[0]) { kn0 = b.nrm[0][i]; kn1 = b.nrm[1][i]; kn2 = b.nrm[2][i]; }
-        int32_t j = i - 1;
-        while (j >= beg && b.id[j] > key) {
-            b.id[j + 1] = b.id[j];
-            b.x[0][j + 1] = b.x[0][j];
-            b.x[1][j + 1] = b.x[1][j];
-            if (dim == 3) b.x[2][j + 1] = b.x[2][j];
-            if (b.rho) b.rho[j + 1] = b.rho[j];
-            if (b.nrm[0]) {
-                b.nrm[0][j + 1] = b.nrm[0][j];
-                b.nrm[1][j + 1] = b.nrm[1][j];
-                b.nrm[2][j + 1] = b.nrm[2][j];
-            }
-            --j;
-        }
-        b.id[j + 1] = key;
-        b.x[0][j + 1] = kx;
-        b.x[1][j + 1] = ky;
-        if (dim == 3) b.x[2][j + 1] = kz;
-        if (b.rho) b.rho[j + 1] = kr;
-        if (b.nrm[0]) { b.nrm[0][j + 1] = kn0; b.nrm[1][j + 1] = kn1; b.nrm[2][j + 1] = kn2; }
-    }
-}
-
-// Crowded grids place particles by rank instead of sorting afterwards: the
-// ids go to their cells in arrival order, then each particle counts the
-// smaller ids of its cell (its place in ascending id order) and moves its
-// record there.
+// Placement without a sort pass: the ids go to their cells in arrival order,
+// then each particle counts the smaller ids of its cell (its place in
+// ascending id order) and moves its record there.
 __global__ void __launch_bounds__(kBlock) k_scatter_id(const int32_t *__restrict__ id, int32_t n,
                                                        const int32_t *__restrict__ cell,
                                                        const int32_t *__restrict__ slot,
@@ -375,9 +314,6 @@ hipError_t scan_counts(const int32_t *counts, int32_t *start, int32_t *partials,
     return hipGetLastError();
 }
 
-// Mean particles per cell from which the rank placement replaces the sort.
-constexpr int64_t kRankOccupancy = 3;
-
 hipError_t bin_particles(int dim, const PBuf &src, const PBuf &dst, int32_t n, const Grid &g,
                          Scratch &sc, Counters *cnt, hipStream_t stream)
 {
@@ -396,16 +332,11 @@ hipError_t bin_particles(int dim, const PBuf &src, const PBuf &dst, int32_t n, c
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = scan_counts(sc.counts, sc.start, sc.partials, g.ncell, stream)) != hipSuccess) return e;
-    if (n > 0 && sc.tmpid && (int64_t)n >= kRankOccupancy * (int64_t)g.ncell) {
+    if (n > 0) {
         hipLaunchKernelGGL(k_scatter_id, dim3(blocks_for(n)), dim3(kBlock), 0, stream, src.id, n,
                            sc.cell, sc.slot, sc.start, sc.tmpid);
         hipLaunchKernelGGL(k_rank_scatter, dim3(blocks_for(n)), dim3(kBlock), 0, stream, src, dst,
                            n, dim, sc.cell, sc.start, sc.tmpid);
-    } else if (n > 0) {
-        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(kBlock), 0, stream, src, dst, n,
-                           dim, sc.cell, sc.slot, sc.start);
-        hipLaunchKernelGGL(k_fixup, dim3(blocks_for(g.ncell)), dim3(kBlock), 0, stream, dst, dim,
-                           sc.start, g.ncell);
     }
     return hipGetLastError();
 }

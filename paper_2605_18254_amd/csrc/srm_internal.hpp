@@ -31,7 +31,7 @@ struct Counters {
 struct Scratch {
     int32_t *cell;      // [n] destination cell per source slot
     int32_t *slot;      // [n] rank within the destination cell (atomic order)
-    int32_t *tmpid;     // [n] ids in arrival order (crowded grids: in-cell ranks)
+    int32_t *tmpid;     // [n] ids in arrival order, for the in-cell ranks
     int32_t *counts;    // [cap] particles per cell
     int32_t *start;     // [cap + 1] exclusive prefix of counts
     int32_t *partials;  // per-block sums of the scan
