@@ -219,6 +219,43 @@ def platelet_extra(max_sweeps):
                        "c_m=0.1*s_target, c_n=c_m/a_t, N_k=N_l=8")
     return out
 
+def n_scaling_extra():
+    """Wall time to reach the target from the uniform start (s = 0) for N =
+    1e3 .. 1e7 spheres in the unit cube at f = 0.35 (the benchmark's
+    parameters), and the fitted exponent of time in N (the paper reports
+    the growth of its run time with N; the sweep count is nearly independent
+    of N)."""
+    import math
+
+    import torch
+
+    import paper_2605_18254_amd as srm
+    import srm_inputs
+
+    rows = []
+    warm = srm.SRM.from_workload(srm_inputs.make("spheres3d", n=1_000), device=True)
+    warm.run(1000)  # first launches load the kernels; keep them out of the timings
+    warm.close()
+    for n in (1_000, 10_000, 100_000, 1_000_000, 10_000_000):
+        w = srm_inputs.make("spheres3d", n=n)
+        g = srm.SRM.from_workload(w, device=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = g.run(1000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        g.close()
+        rows.append({"n": n, "converged": st == 0, "sweeps": info["sweeps"],
+                     "passes": info["passes"], "s": dt, "updates_per_s": info["updates"] / dt})
+        _say(f"n-scaling: {rows[-1]}")
+    big = [r for r in rows if r["n"] >= 100_000]
+    xs = [math.log(r["n"]) for r in big]
+    ys = [math.log(r["s"]) for r in big]
+    mx, my = sum(xs) / len(xs), sum(ys) / len(ys)
+    slope = sum((x - mx) * (y - my) for x, y in zip(xs, ys)) / sum((x - mx) ** 2 for x in xs)
+    return {"workload": "spheres3d, unit cube, f 0.35, seed 1, uniform start at s = 0",
+            "runs": rows, "time_exponent_n_ge_1e5": slope}
+
 def grad_extra(steps, steer_steps):
     """Soft g(r) (64 Gaussian bins up to 5r) + overlap energy, forward and
     hand-written backward, on N = 2e5 spheres grown by SRM to f = 0.30; then
@@ -394,7 +431,8 @@ def main():
                       "frac": (phase_bytes + BIN_BYTES * w.n * passes) / dt / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_extras:
-        out["extras"] = {"platelets": platelet_extra(3000),
+        out["extras"] = {"n_scaling": n_scaling_extra(),
+                         "platelets": platelet_extra(3000),
                          "batched": batched_extra(args.batch_sweeps),
                          "gradient": grad_extra(20, 10)}
     if not args.no_cpu_baseline:

@@ -175,6 +175,19 @@ srm_status srm_pass(srm_ctx *ctx, double grid_s, double radius_s, int32_t kind, 
 /* Accept codes of the last pass run by srm_sweep or srm_pass, id order. */
 srm_status srm_last_acc(srm_ctx *ctx, uint8_t *acc_by_id);
 
+/* Nearest-neighbour distances of the committed configuration, the
+ * structure descriptor the paper compares its microstructures by (the
+ * nearest-neighbour distance distributions of Sec. 4, Fig. 4d): for every
+ * particle the smallest minimum-image centre distance sqrt(q),
+ * q = (d0*d0 + d1*d1) + d2*d2, to another particle with q < r_max^2, or
+ * +infinity if there is none (0 < r_max <= L/2).  dist_by_id (host, n
+ * doubles, nullable) receives the distances in id order.  hist (host,
+ * nbins uint64 counts, nullable; then 1 <= nbins <= 65536) receives the
+ * counts of bin (int)(d * (nbins / r_max)) over the particles with a finite
+ * d in range.  Balls only.  Errors: SRM_EINVAL. */
+srm_status srm_nearest(srm_ctx *ctx, double r_max, double *dist_by_id, int32_t nbins,
+                       uint64_t *hist);
+
 /* ---- differentiable descriptor: soft g(r) + overlap energy -------------- */
 
 /* A workspace for configurations of n particles in a fixed periodic box.

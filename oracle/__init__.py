@@ -97,12 +97,14 @@ def lib():
         L.o_pairs_brute.restype = C.c_int64
         L.o_rdf_brute.argtypes = [C.POINTER(State), C.c_int32, C.c_double,
                                   C.POINTER(C.c_uint64)]
+        L.o_nearest_brute.argtypes = [C.POINTER(State), C.c_double, dp]
         L.o_disks_intersect.argtypes = [dp, dp, C.c_double, dp, dp, C.c_double, dp]
         L.o_softrdf_fwd.argtypes = [C.POINTER(SoftParams), C.c_int64, dp, dp, dp, dp]
         L.o_softrdf_grad.argtypes = [C.POINTER(SoftParams), C.c_int64, dp, dp, dp, C.c_double,
                                      dp, dp]
         L.o_disks_intersect.restype = C.c_int
-        for f in ("o_pass", "o_overlap", "o_sweep", "o_run", "o_rdf_brute", "o_bin"):
+        for f in ("o_pass", "o_overlap", "o_sweep", "o_run", "o_rdf_brute", "o_bin",
+                  "o_nearest_brute"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -312,6 +314,13 @@ class Oracle:
         _check(lib().o_rdf_brute(C.byref(self.st), int(nbins), float(r_max),
                                  counts.ctypes.data_as(C.POINTER(C.c_uint64))))
         return counts
+
+    def nearest_brute(self, r_max: float) -> np.ndarray:
+        """Distance to the nearest other particle (q < r_max^2), id order;
+        +inf where there is none."""
+        dist = np.empty(self.n, dtype=np.float64)
+        _check(lib().o_nearest_brute(C.byref(self.st), float(r_max), _dp(dist)))
+        return dist
 
     def soa(self) -> np.ndarray:
         return np.ascontiguousarray(self.pos[:, : self.dim].T)

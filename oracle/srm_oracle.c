@@ -640,6 +640,29 @@ int o_rdf_brute(const o_state *st, int32_t nbins, double r_max, uint64_t *counts
     return O_OK;
 }
 
+/* Nearest-neighbour distances (the structure descriptor of the paper's
+ * Sec. 4 comparison, Fig. 4d): for every particle i the square root of the
+ * smallest q_ij over all j != i with q_ij < r_max^2, or +infinity when
+ * there is none.  All pairs. */
+int o_nearest_brute(const o_state *st, double r_max, double *dist)
+{
+    double r2 = r_max * r_max;
+    for (int64_t i = 0; i < st->p.n; ++i) {
+        double best = r2;
+        int found = 0;
+        for (int64_t j = 0; j < st->p.n; ++j) {
+            if (j == i) continue;
+            double q = o_pair_q(st, i, j);
+            if (q < best) {
+                best = q;
+                found = 1;
+            }
+        }
+        dist[i] = found ? sqrt(best) : INFINITY;
+    }
+    return O_OK;
+}
+
 /* ------------------------------------------------------------------ */
 /* Soft-binned radial distribution and overlap penalty (differentiable  */
 /* steering of configurations toward a target g(r)).                   */

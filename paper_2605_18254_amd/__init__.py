@@ -24,7 +24,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 MAIN, SHAKE = 0, 1
 OK, EINVAL, ENOMEM, EDEVICE, EOVERLAP, ENOTCONV, ECAPACITY = 0, -1, -2, -3, -4, -5, -6
 
-SYMBOLS = ["srm_init", "srm_sweep", "srm_run_to_fraction", "srm_pairs", "srm_rdf",
+SYMBOLS = ["srm_init", "srm_sweep", "srm_run_to_fraction", "srm_pairs", "srm_rdf", "srm_nearest",
            "srm_get_state", "srm_free", "srm_last_error", "srm_grid", "srm_cells", "srm_pass",
            "srm_last_acc", "srm_set_state", "srm_softrdf_create", "srm_softrdf_forward",
            "srm_softrdf_backward", "srm_softrdf_free", "srm_profile_enable", "srm_profile_read",
@@ -90,6 +90,7 @@ def lib():
     L.srm_run_to_fraction.argtypes = [vp, C.c_int32, C.POINTER(RunInfo)]
     L.srm_pairs.argtypes = [vp, C.c_double, C.c_int64, vp, C.POINTER(C.c_int64), C.c_int32]
     L.srm_rdf.argtypes = [vp, C.c_int32, C.c_double, C.POINTER(C.c_uint64), dp]
+    L.srm_nearest.argtypes = [vp, C.c_double, dp, C.c_int32, C.POINTER(C.c_uint64)]
     L.srm_get_state.argtypes = [vp, vp, vp, dp, C.POINTER(C.c_int64), C.c_int32]
     L.srm_free.argtypes = [vp]
     L.srm_last_error.argtypes = []
@@ -315,6 +316,18 @@ class SRM:
         _check(lib().srm_pairs(self._ctx, float(gap), cnt.value, C.c_void_p(out.ctypes.data),
                                C.byref(cnt), MEM_HOST))
         return out[: cnt.value]
+
+    def nearest(self, r_max: float, nbins: int = 0):
+        """(distance to the nearest other particle by id, +inf if none within
+        r_max; histogram of those distances over nbins bins on [0, r_max),
+        or None when nbins is 0)."""
+        dist = np.empty(self.n, dtype=np.float64)
+        hist = np.zeros(max(nbins, 1), dtype=np.uint64)
+        _check(lib().srm_nearest(self._ctx, float(r_max),
+                                 dist.ctypes.data_as(C.POINTER(C.c_double)), int(nbins),
+                                 hist.ctypes.data_as(C.POINTER(C.c_uint64)) if nbins > 0
+                                 else None))
+        return dist, (hist if nbins > 0 else None)
 
     def rdf(self, nbins: int, r_max: float):
         counts = np.zeros(nbins, dtype=np.uint64)

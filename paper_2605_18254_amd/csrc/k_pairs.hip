@@ -157,6 +157,67 @@ __global__ void __launch_bounds__(kBlock) k_rdf(PairArgs a, int32_t nbins, doubl
     }
 }
 
+// Nearest neighbour of the particle in slot p within r2 = r_max^2: the
+// minimum of q over the stencil (order-independent), written by id; then
+// its histogram bin (LDS counts when nbins fits, else direct atomics).
+template <int DIM, bool SHARED>
+__global__ void __launch_bounds__(kBlock) k_nearest(PairArgs a, double r2, double *__restrict__ dist,
+                                                    int32_t nbins, double inv,
+                                                    unsigned long long *__restrict__ counts)
+{
+    extern __shared__ uint32_t hist[];
+    if (SHARED) {
+        for (int32_t b = threadIdx.x; b < nbins; b += blockDim.x) hist[b] = 0;
+        __syncthreads();
+    }
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < a.n) {
+        const int32_t cx = cell_coord(a.buf.x[0][p], a.g.inv_w[0], a.g.na[0]);
+        const int32_t cy = cell_coord(a.buf.x[1][p], a.g.inv_w[1], a.g.na[1]);
+        const int32_t cz = (DIM == 3) ? cell_coord(a.buf.x[2][p], a.g.inv_w[2], a.g.na[2]) : 0;
+        int32_t lo[Rows<DIM>::kRanges], hi[Rows<DIM>::kRanges];
+        stencil_slices<DIM>(a.g, a.start, cx, cy, cz, lo, hi);
+        const double xp = a.buf.x[0][p], yp = a.buf.x[1][p];
+        const double zp = (DIM == 3) ? a.buf.x[2][p] : 0.0;
+        double best = r2;
+        bool found = false;
+#pragma unroll
+        for (int r = 0; r < Rows<DIM>::kRanges; ++r) {
+            for (int32_t q = lo[r]; q < hi[r]; ++q) {
+                if (q == p) continue;
+                const double dx = min_image(xp - a.buf.x[0][q], a.g.box[0], a.g.half[0]);
+                const double dy = min_image(yp - a.buf.x[1][q], a.g.box[1], a.g.half[1]);
+                double qq = dx * dx + dy * dy;
+                if (DIM == 3) {
+                    const double dz = min_image(zp - a.buf.x[2][q], a.g.box[2], a.g.half[2]);
+                    qq = qq + dz * dz;
+                }
+                if (qq < best) {
+                    best = qq;
+                    found = true;
+                }
+            }
+        }
+        const double d = found ? __builtin_sqrt(best) : __builtin_inf();
+        if (dist) dist[a.buf.id[p]] = d;
+        if (counts && found) {
+            const double x = d * inv;
+            if (x < (double)nbins) {
+                const int32_t b = (int32_t)x;
+                if (b < nbins) {
+                    if (SHARED) atomicAdd(&hist[b], 1u);
+                    else atomicAdd(&counts[b], 1ull);
+                }
+            }
+        }
+    }
+    if (SHARED) {
+        __syncthreads();
+        for (int32_t b = threadIdx.x; b < nbins; b += blockDim.x)
+            if (hist[b]) atomicAdd(&counts[b], (unsigned long long)hist[b]);
+    }
+}
+
 }  // namespace
 
 hipError_t pairs_count(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
@@ -207,6 +268,30 @@ hipError_t rdf_counts(int dim, const PBuf &b, const int32_t *start, const Grid &
                                        stream, a, nbins, inv, counts);
         else hipLaunchKernelGGL((k_rdf<2, false>), dim3(blocks_for(n)), dim3(kBlock), 0, stream,
                                 a, nbins, inv, counts);
+    }
+    return hipGetLastError();
+}
+
+hipError_t nearest(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
+                   double r_max, double *dist, int32_t nbins, unsigned long long *counts,
+                   hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const PairArgs a{b, start, g, n, SRM_BALL, 0.0, 0.0};
+    const double r2 = r_max * r_max;
+    const double inv = counts ? (double)nbins / r_max : 0.0;
+    const bool shared = counts && nbins <= 8192;
+    const size_t lds = shared ? (size_t)nbins * sizeof(uint32_t) : 0;
+    if (dim == 3) {
+        if (shared) hipLaunchKernelGGL((k_nearest<3, true>), dim3(blocks_for(n)), dim3(kBlock), lds,
+                                       stream, a, r2, dist, nbins, inv, counts);
+        else hipLaunchKernelGGL((k_nearest<3, false>), dim3(blocks_for(n)), dim3(kBlock), 0,
+                                stream, a, r2, dist, nbins, inv, counts);
+    } else {
+        if (shared) hipLaunchKernelGGL((k_nearest<2, true>), dim3(blocks_for(n)), dim3(kBlock), lds,
+                                       stream, a, r2, dist, nbins, inv, counts);
+        else hipLaunchKernelGGL((k_nearest<2, false>), dim3(blocks_for(n)), dim3(kBlock), 0,
+                                stream, a, r2, dist, nbins, inv, counts);
     }
     return hipGetLastError();
 }

@@ -744,6 +744,36 @@ srm_status srm_rdf(srm_ctx *c, int32_t nbins, double r_max, uint64_t *counts, do
     return SRM_OK;
 }
 
+srm_status srm_nearest(srm_ctx *c, double r_max, double *dist_by_id, int32_t nbins,
+                       uint64_t *hist)
+{
+    if (!c) return fail(SRM_EINVAL, "ctx is NULL");
+    if (c->p.shape != SRM_BALL) return fail(SRM_EINVAL, "nearest neighbours are for balls");
+    if (hist && (nbins < 1 || nbins > 65536)) return fail(SRM_EINVAL, "nbins out of range");
+    double lmin = c->p.box[0];
+    for (int a = 1; a < c->dim; ++a) lmin = c->p.box[a] < lmin ? c->p.box[a] : lmin;
+    if (!(r_max > 0.0) || !(r_max <= 0.5 * lmin)) return fail(SRM_EINVAL, "need 0 < r_max <= L/2");
+    const Grid g = cutoff_grid(c, r_max);
+    srm_status st;
+    if ((st = bin(c, c->P, c->T, g))) return st;
+    DevArena d;
+    if (dist_by_id) HIP_TRY(hipMalloc(&d.p[0], (size_t)c->n * sizeof(double)));
+    if (hist) {
+        HIP_TRY(hipMalloc(&d.p[1], (size_t)nbins * sizeof(uint64_t)));
+        HIP_TRY(launch_fill_i32((int32_t *)d.p[1], 2 * (int64_t)nbins, 0, c->stream));
+    }
+    HIP_TRY(nearest(c->dim, c->T, c->sc.start, g, c->n, r_max, (double *)d.p[0], nbins,
+                    (unsigned long long *)d.p[1], c->stream));
+    if (dist_by_id)
+        HIP_TRY(hipMemcpyAsync(dist_by_id, d.p[0], (size_t)c->n * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream));
+    if (hist)
+        HIP_TRY(hipMemcpyAsync(hist, d.p[1], (size_t)nbins * sizeof(uint64_t),
+                               hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SRM_OK;
+}
+
 srm_status srm_profile_enable(srm_ctx *c, int32_t on)
 {
     if (!c) return fail(SRM_EINVAL, "ctx is NULL");

@@ -104,6 +104,11 @@ hipError_t pairs_emit(int dim, const PBuf &b, const int32_t *start, const Grid &
                       int32_t *ij, hipStream_t stream);
 hipError_t rdf_counts(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
                       int32_t nbins, double inv, unsigned long long *counts, hipStream_t stream);
+// Nearest-neighbour distance (by id, nullable) and its histogram (nullable)
+// for every particle, searched within r_max (grid cells >= r_max).
+hipError_t nearest(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
+                   double r_max, double *dist, int32_t nbins, unsigned long long *counts,
+                   hipStream_t stream);
 
 // Soft-binned g(r) + overlap energy and its gradient (k_softrdf.hip).
 int32_t soft_blocks(int32_t n);

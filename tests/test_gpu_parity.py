@@ -379,6 +379,28 @@ def test_rdf_counts_match_oracle(srm, oracle_lib, dim, n, nbins):
     g.close()
 
 
+@pytest.mark.parametrize("dim,n,nbins,r_scale", [(2, 3000, 50, 3.0), (3, 8000, 40, 2.4),
+                                                 (3, 6000, 20000, 2.2)])
+def test_nearest_neighbours_match_oracle(srm, oracle_lib, dim, n, nbins, r_scale):
+    """Nearest-neighbour distances of an SRM configuration (every value,
+    bit for bit, +inf where none is within r_max; r_max = 2.2 radii leaves
+    some particles without a neighbour) and their histogram (LDS counts and,
+    for 20000 bins, direct atomics)."""
+    w = _mk(dim, n, 150 + n % 11, 0.35)
+    o = oracle_lib.Oracle.from_workload(w)
+    o.run(3000)
+    g = _gpu_from_oracle(srm, o, w)
+    r_max = r_scale * o.s
+    dist, hist = g.nearest(r_max, nbins)
+    ref = o.nearest_brute(r_max)
+    assert np.array_equal(dist, ref)
+    fin = ref[np.isfinite(ref)]
+    b = (fin * (nbins / r_max)).astype(np.int64)
+    assert np.array_equal(hist, np.bincount(b[b < nbins], minlength=nbins).astype(np.uint64))
+    _say(f"nearest {dim}D: {int(np.isinf(ref).sum())} without a neighbour within r_max")
+    g.close()
+
+
 # ------------------------------------------------------------ batched RVEs
 
 def test_batch_members_bitidentical_to_solo_runs(srm, oracle_lib):

@@ -177,3 +177,49 @@ def test_disks_dense_sampling(oracle_lib):
             assert not got
             agree += 1
     assert agree > 200
+
+
+# ------------------------------------------------------ nearest neighbours
+
+def test_nearest_on_a_lattice_and_across_the_boundary(oracle_lib):
+    """A simple cubic lattice of spacing 1/8 in the unit cube: every nearest
+    distance is the spacing (to rounding); two particles 0.02 apart across
+    the periodic face find each other; a lone particle gets +inf."""
+    m = 8
+    g = (np.arange(m) + 0.5) / m
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
+    o = oracle_lib.Oracle(dim=3, n=pos.shape[1], s_target=0.01, c_w=0.01, c_m=0.001,
+                          n_k=8, n_l=8, seed=1, pos=pos)
+    d = o.nearest_brute(0.3)
+    assert np.all(np.abs(d - 1.0 / m) <= 4e-16)
+    pos2 = np.array([[0.99, 0.01], [0.5, 0.5], [0.5, 0.5]])
+    o2 = oracle_lib.Oracle(dim=3, n=2, s_target=0.001, c_w=0.01, c_m=0.0001, n_k=8, n_l=8,
+                           seed=1, pos=pos2)
+    assert np.allclose(o2.nearest_brute(0.3), 0.02, rtol=0, atol=1e-15)
+    assert np.all(np.isinf(o2.nearest_brute(0.01)))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nearest_matches_a_kd_tree(oracle_lib, dim):
+    """Random points: the all-pairs nearest distances equal scipy's periodic
+    k-d tree query (another algorithm and another rounding order) to 1e-14
+    relative, and the cutoff turns exactly the far ones into +inf."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(11 + dim)
+    n = 1500
+    pos = rng.random((dim, n))
+    o = oracle_lib.Oracle(dim=dim, n=n, s_target=1e-4, c_w=0.01, c_m=1e-5, n_k=8, n_l=8,
+                          seed=1, pos=pos)
+    r_max = 0.2
+    d = o.nearest_brute(r_max)
+    ref, _ = cKDTree(pos.T, boxsize=1.0).query(pos.T, k=2)
+    ref = ref[:, 1]
+    fin = ref < r_max * (1 - 1e-12)
+    assert np.allclose(d[fin], ref[fin], rtol=1e-14, atol=0)
+    assert np.all(np.isinf(d[ref > r_max * (1 + 1e-12)]))
+    med = float(np.median(ref))
+    d_small = o.nearest_brute(med)
+    clear = np.abs(ref - med) > 1e-12 * med
+    assert np.array_equal(np.isinf(d_small)[clear], (ref >= med)[clear])
+    assert np.array_equal(d_small[~np.isinf(d_small)], d[~np.isinf(d_small)])
