@@ -177,7 +177,7 @@ srm_status srm_last_acc(srm_ctx *ctx, uint8_t *acc_by_id);
 
 /* Nearest-neighbour distances of the committed configuration, the
  * structure descriptor the paper compares its microstructures by (the
- * nearest-neighbour distance distributions of Sec. 4, Fig. 4d): for every
+ * nearest-neighbour distance distributions of Sec. 3.2, Fig. 4d): for every
  * particle the smallest minimum-image centre distance sqrt(q),
  * q = (d0*d0 + d1*d1) + d2*d2, to another particle with q < r_max^2, or
  * +infinity if there is none (0 < r_max <= L/2).  dist_by_id (host, n

@@ -641,7 +641,7 @@ int o_rdf_brute(const o_state *st, int32_t nbins, double r_max, uint64_t *counts
 }
 
 /* Nearest-neighbour distances (the structure descriptor of the paper's
- * Sec. 4 comparison, Fig. 4d): for every particle i the square root of the
+ * Sec. 3.2 comparison, Fig. 4d): for every particle i the square root of the
  * smallest q_ij over all j != i with q_ij < r_max^2, or +infinity when
  * there is none.  All pairs. */
 int o_nearest_brute(const o_state *st, double r_max, double *dist)
