@@ -60,12 +60,12 @@ __global__ void __launch_bounds__(64) k_migrate_wave(PassArgs a, ColourLattice L
 // every cell its lanes can touch -- into LDS as SoA positions with a local
 // CSR index; each thread copies whole cells so neighbouring threads read
 // neighbouring addresses.  Then, with four lanes (a quad) per task:
-//  A. near lists, in parallel over all particles of the tile's own cells:
-//     the candidates of the 3^dim stencil outside the particle's own cell
-//     whose distance to its old position is at most R_i + R_j + 2 c_m.  No
-//     such candidate moves during this colour phase, and every particle a
-//     trial within c_m of the old position can touch is among them (the
-//     exact test decides).
+//  A. near lists, in parallel over all particles of the tile's own cells,
+//     one lane per (particle, stencil row): the candidates of the 3^dim
+//     stencil outside the particle's own cell whose distance to its old
+//     position is at most R_i + R_j + 2 c_m.  No such candidate moves
+//     during this colour phase, and every particle a trial within c_m of the
+//     old position can touch is among them (the exact test decides).
 //  B. the sequential part, one quad per cell, particles in ascending id
 //     order: lane j of the quad draws trial l = base + j and tests it exactly
 //     against the near list and the other particles of its own cell at their
@@ -84,11 +84,11 @@ struct QuadCfg {
     static constexpr int kCells = (DIM == 3) ? R * R * R : R * R;
     static constexpr int kThreads = 256;
     static constexpr int kPer = (kCells + kThreads - 1) / kThreads;
-    static constexpr int kNear = 12;    // near-list entries per particle
+    static constexpr int kNear = 11;    // near-list entries per particle
     static constexpr int kOwn = 160;    // particles of the tile's own cells
     // LDS capacity in particles: the workgroup stays under 40 KB so four
     // workgroups (sixteen waves) fit a CU.
-    static constexpr int kCap = (DIM == 3) ? (POLY ? 1088 : 1464) : (POLY ? 1472 : 2176);
+    static constexpr int kCap = (DIM == 3) ? (POLY ? 1080 : 1456) : (POLY ? 1464 : 2168);
 };
 
 struct TileLattice {
@@ -182,46 +182,30 @@ __device__ __forceinline__ bool lds_hits(const PassArgs &a, const double *sx, co
     return false;
 }
 
-// Phase A for the particle in LDS slot p of own cell [ob, oe): the quad's
-// lanes split the stencil's candidates four ways and append the near ones
-// to nl; *count gets their number, or 255 when nl overflowed.
+// Phase A, one stencil row of the particle in LDS slot p (own cell [ob, oe)):
+// append to nl every candidate of slots [lo, hi) outside the own cell within
+// R_i + R_j + 2 c_m of p; *count counts all of them (beyond kNear the list is
+// incomplete and phase B scans the whole stencil instead).
 template <int DIM, bool POLY, bool GENERAL>
-__device__ __forceinline__ void build_near(const PassArgs &a, const double *sx, const double *sy,
-                                           const double *sz, const double *srho,
-                                           const uint16_t *lst, int32_t rx, int32_t ry,
-                                           int32_t rz, int32_t ob, int32_t oe, int32_t p,
-                                           uint16_t *nl, uint8_t *count, int sub)
+__device__ __forceinline__ void near_row(const PassArgs &a, const double *sx, const double *sy,
+                                         const double *sz, const double *srho, int32_t lo,
+                                         int32_t hi, int32_t ob, int32_t oe, int32_t p,
+                                         uint16_t *nl, int32_t *count)
 {
     using C = QuadCfg<DIM, POLY>;
     const double px = sx[p], py = sy[p], pz = (DIM == 3) ? sz[p] : 0.0;
     const double Ri = POLY ? a.s * srho[p] : a.s;
     const double margin = 2.0 * a.c_m;
-    int32_t nn = 0;
-#pragma unroll
-    for (int iz = 0; iz < (DIM == 3 ? 3 : 1); ++iz) {
-#pragma unroll
-        for (int iy = 0; iy < 3; ++iy) {
-            const int32_t row = (ry + iy - 1) * C::R + ((DIM == 3) ? (rz + iz - 1) * C::R * C::R : 0);
-            const int32_t lo = lst[row + rx - 1], hi = lst[row + rx + 2];
-            for (int32_t c0 = lo; c0 < hi; c0 += 4) {
-                const int32_t c = c0 + sub;
-                bool keep = false;
-                if (c < hi && (c < ob || c >= oe)) {
-                    const double qq = sq_dist<DIM, GENERAL>(a.g, px, py, pz, sx[c], sy[c],
-                                                            (DIM == 3) ? sz[c] : 0.0);
-                    const double reach = (POLY ? Ri + a.s * srho[c] : Ri + Ri) + margin;
-                    keep = qq <= reach * reach;
-                }
-                const uint32_t qb = quad_bits(__ballot(keep));
-                if (keep) {
-                    const int32_t slot = nn + __popc(qb & ((1u << sub) - 1u));
-                    if (slot < C::kNear) nl[slot] = (uint16_t)c;
-                }
-                nn += __popc(qb);
-            }
+    for (int32_t c = lo; c < hi; ++c) {
+        if (c >= ob && c < oe) continue;
+        const double qq = sq_dist<DIM, GENERAL>(a.g, px, py, pz, sx[c], sy[c],
+                                                (DIM == 3) ? sz[c] : 0.0);
+        const double reach = (POLY ? Ri + a.s * srho[c] : Ri + Ri) + margin;
+        if (qq <= reach * reach) {
+            const int32_t slot = atomicAdd(count, 1);
+            if (slot < C::kNear) nl[slot] = (uint16_t)c;
         }
     }
-    if (sub == 0) *count = (uint8_t)(nn > C::kNear ? 255 : nn);
 }
 
 // Phase B test of one trial position y of the particle in LDS slot p.
@@ -276,7 +260,7 @@ __global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
     __shared__ uint16_t lst[C::kCells + 1];
     __shared__ uint16_t obase[65];
     __shared__ uint16_t nearl[C::kOwn][C::kNear];
-    __shared__ uint8_t ncnt[C::kOwn];
+    __shared__ int32_t ncnt[C::kOwn];  // near-list lengths (may exceed kNear: overflow)
     __shared__ int32_t wtot[4];
 
     // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous
@@ -403,13 +387,19 @@ __global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
         obase[tid] = (uint16_t)(incl - m_);
         if (tid == 63) obase[64] = (uint16_t)(incl > 65535 ? 65535 : incl);
     }
+    for (int32_t o = tid; o < C::kOwn; o += 256) ncnt[o] = 0;
     __syncthreads();
     const int32_t nown = obase[64];
     const bool use_near = nown <= C::kOwn;
 
-    // 5. phase A: near lists for every own particle (quad per particle)
+    // 5. phase A: near lists for every own particle.  One lane per (own
+    // particle, stencil row): the row's candidates outside the particle's
+    // cell within R_i + R_j + 2 c_m of its old position are appended
+    // (LDS atomics; the order of a list does not matter).
     if (use_near) {
-        for (int32_t o = q; o < nown; o += 64) {
+        constexpr int kRowsA = Rows<DIM>::kRows;
+        for (int32_t w = tid; w < nown * kRowsA; w += 256) {
+            const int32_t o = w / kRowsA, row = w - o * kRowsA;
             int32_t klo = 0, khi = 63;
             while (klo < khi) {
                 const int32_t mid = (klo + khi + 1) >> 1;
@@ -426,12 +416,15 @@ __global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
             const int32_t cy_ = 2 * (C::T * ty + ly_) + L.off[1];
             const int32_t cz_ = (DIM == 3) ? 2 * (C::T * tz + lz_) + L.off[2] : 0;
             const int32_t rx_ = 2 * lx_ + 1, ry_ = 2 * ly_ + 1, rz_ = (DIM == 3) ? 2 * lz_ + 1 : 0;
+            const int32_t iy = row % 3, iz = row / 3;
+            const int32_t r0 = (ry_ + iy - 1) * C::R + ((DIM == 3) ? (rz_ + iz - 1) * C::R * C::R : 0);
+            const int32_t lo = lst[r0 + rx_ - 1], hi = lst[r0 + rx_ + 2];
             if (is_interior<DIM>(a.g, cx_, cy_, cz_))
-                build_near<DIM, POLY, false>(a, sx, sy, sz, srho, lst, rx_, ry_, rz_, ob, oe, p,
-                                             nearl[o], &ncnt[o], sub);
+                near_row<DIM, POLY, false>(a, sx, sy, sz, srho, lo, hi, ob, oe, p, nearl[o],
+                                           &ncnt[o]);
             else
-                build_near<DIM, POLY, true>(a, sx, sy, sz, srho, lst, rx_, ry_, rz_, ob, oe, p,
-                                            nearl[o], &ncnt[o], sub);
+                near_row<DIM, POLY, true>(a, sx, sy, sz, srho, lo, hi, ob, oe, p, nearl[o],
+                                          &ncnt[o]);
         }
     }
     __syncthreads();
@@ -457,7 +450,7 @@ __global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
         const int32_t o = o0 + (p - ob);
         const double px = sx[p], py = sy[p], pz = (DIM == 3) ? sz[p] : 0.0;
         const double Ri = POLY ? a.s * srho[p] : a.s;
-        const int32_t nn = use_near ? (int32_t)ncnt[o] : 255;
+        const int32_t nn = use_near ? (ncnt[o] > C::kNear ? 255 : ncnt[o]) : 255;
         const uint16_t *nl = use_near ? nearl[o] : nullptr;
         const uint32_t id = (uint32_t)a.buf.id[gp];
         uint8_t code = 0;
