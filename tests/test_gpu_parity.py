@@ -401,6 +401,34 @@ def test_nearest_neighbours_match_oracle(srm, oracle_lib, dim, n, nbins, r_scale
     g.close()
 
 
+def test_nearest_edge_cases_and_errors(srm, oracle_lib):
+    """One particle has no neighbour (+inf, empty histogram); two particles
+    find each other across the periodic face; r_max beyond L/2, a bad bin
+    count and a platelet context are rejected with SRM_EINVAL."""
+    w1 = _mk(3, 1, 171, 0.2)
+    g1 = srm.SRM.from_workload(w1)
+    d, h = g1.nearest(0.4, 8)
+    assert np.isinf(d).all() and not h.any()
+    g1.close()
+    pos = np.array([[0.995, 0.005], [0.5, 0.5], [0.25, 0.25]])
+    g2 = srm.SRM(dim=3, n=2, s_target=0.001, c_w=0.01, c_m=1e-4, n_k=8, n_l=8, seed=3, pos=pos)
+    o2 = oracle_lib.Oracle(dim=3, n=2, s_target=0.001, c_w=0.01, c_m=1e-4, n_k=8, n_l=8, seed=3,
+                           pos=pos)
+    d, _ = g2.nearest(0.1)
+    assert np.array_equal(d, o2.nearest_brute(0.1)) and abs(d[0] - 0.01) < 1e-15
+    for bad in (lambda: g2.nearest(0.6), lambda: g2.nearest(0.0), lambda: g2.nearest(0.1, 70000)):
+        with pytest.raises(srm.SrmError) as e:
+            bad()
+        assert e.value.status == srm.EINVAL
+    g2.close()
+    wp = srm_inputs.make("platelets", n=500, f_target=0.01)
+    gp = srm.SRM.from_workload(wp)
+    with pytest.raises(srm.SrmError) as e:
+        gp.nearest(0.2)
+    assert e.value.status == srm.EINVAL
+    gp.close()
+
+
 # ------------------------------------------------------------ batched RVEs
 
 def test_batch_members_bitidentical_to_solo_runs(srm, oracle_lib):
