@@ -148,6 +148,9 @@ struct WaveLds {
     WaveOwn own[kWaveOwn];
     int32_t nn[kWaveOwn];
     int32_t near[kWaveOwn * kWaveNear];  // slot q >= 0, or -(k + 1) for own particle k
+    int32_t id[kWaveOwn];
+    int32_t nfail;
+    int32_t fail[kWaveOwn];  // own indices that rejected every trial
 };
 
 template <int DIM>
@@ -244,7 +247,9 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
         o.r = POLY ? a.s * a.buf.rho[beg + k] : a.s;
         L.own[k] = o;
         L.nn[k] = 0;
+        L.id[k] = a.buf.id[beg + k];
     }
+    if (lane == 0) L.nfail = 0;
     __syncthreads();
     // A. near lists
 #pragma unroll
@@ -276,12 +281,31 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
         }
     }
     __syncthreads();
-    // B. the sequential part
+    // B. the sequential part.  A lane's near-list candidate outside the cell
+    // does not move in this phase, so it is fetched one particle ahead (its
+    // load overlaps the current particle's work); cell mates are read from
+    // LDS at test time.
+    auto fetch = [&](int32_t kk, double &fx, double &fy, double &fz, double &fr) {
+        const int32_t mm = L.nn[kk];
+        if (mm < 1 || mm > kWaveNear) return;
+        const int32_t gg = lane / mm;
+        if (gg >= 64 / mm) return;
+        const int32_t ref = L.near[kk * kWaveNear + (lane - gg * mm)];
+        if (ref < 0) return;
+        fx = X[ref];
+        fy = Y[ref];
+        fz = (DIM == 3) ? Z[ref] : 0.0;
+        fr = POLY ? a.s * a.buf.rho[ref] : a.s;
+    };
+    double nx = 0.0, ny = 0.0, nz = 0.0, nr = 0.0;
+    fetch(0, nx, ny, nz, nr);
     for (int32_t k = 0; k < cnt; ++k) {
         const int32_t p = beg + k;
         const WaveOwn me = L.own[k];
-        const uint32_t id = (uint32_t)a.buf.id[p];
+        const uint32_t id = (uint32_t)L.id[k];
         const int32_t m = L.nn[k];
+        const double qx = nx, qy = ny, qz = nz, qr = nr;
+        if (k + 1 < cnt) fetch(k + 1, nx, ny, nz, nr);
         int32_t code = 0;
         double wx = 0.0, wy = 0.0, wz = 0.0;
         if (m == 0) {
@@ -292,14 +316,21 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
             const int32_t G = 64 / m;
             const int32_t g = lane / m, j = lane - g * m;
             const unsigned long long seg = (m == 64) ? ~0ull : ((1ull << m) - 1ull);
+            const int32_t ref = L.near[k * kWaveNear + j];
             for (int32_t l0 = 1; l0 <= a.n_l && code == 0; l0 += G) {
                 const int32_t l = l0 + g;
                 const bool active = g < G && l <= a.n_l;
                 double yx, yy, yz;
                 wave_trial<DIM>(a, id, active ? l : l0, me.x, me.y, me.z, yx, yy, yz);
-                const bool hit =
-                    active && wave_ref_hit<DIM, POLY>(a, L, L.near[k * kWaveNear + j], yx, yy, yz,
-                                                      me.r);
+                bool hit = false;
+                if (active) {
+                    if (ref < 0) {
+                        const WaveOwn o = L.own[-ref - 1];
+                        hit = wave_hit<DIM, POLY>(a, yx, yy, yz, me.r, o.x, o.y, o.z, o.r);
+                    } else {
+                        hit = wave_hit<DIM, POLY>(a, yx, yy, yz, me.r, qx, qy, qz, qr);
+                    }
+                }
                 const unsigned long long hits = __ballot(hit);
                 int32_t win = -1;
                 for (int32_t gg = 0; gg < G && l0 + gg <= a.n_l; ++gg) {
@@ -346,11 +377,20 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
                 a.buf.x[0][p] = wx;
                 a.buf.x[1][p] = wy;
                 if (DIM == 3) a.buf.x[2][p] = wz;
+            } else {
+                L.fail[L.nfail++] = k;
             }
             a.acc[p] = (uint8_t)code;
-            if (code == 0) a.failed[1 + atomicAdd(&a.failed[0], 1)] = p;
         }
         __syncthreads();
+    }
+    // the cell's failures go to the global list once, off the chain
+    const int32_t nf = L.nfail;
+    if (nf > 0) {
+        int32_t base = 0;
+        if (lane == 0) base = atomicAdd(&a.failed[0], nf);
+        base = __shfl(base, 0, 64);
+        for (int32_t i = lane; i < nf; i += 64) a.failed[1 + base + i] = beg + L.fail[i];
     }
 }
 
