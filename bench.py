@@ -382,6 +382,16 @@ def main():
     prof = g.profile()
     final = info
     g.close()
+    # trial moves of the same sweeps, counted on an identical untimed replay
+    # (the count is a reduction per pass, kept out of the timed region)
+    g = srm.SRM.from_workload(w, device=True)
+    for _ in range(args.warmup):
+        g.sweep()
+    g.profile(enable=False, trials=True)
+    for _ in range(args.steps):
+        g.sweep()
+    trials = g.profile()["trials"]
+    g.close()
 
     updates = w.n * passes
     value = updates / dt
@@ -424,6 +434,8 @@ def main():
                      "phase_floor_bytes_per_launch": floor_per_launch,
                      "phase_floor_gbs": floor_per_launch / avg_launch_s / 1e9,
                      "traffic_source": traffic["source"] if traffic else None},
+        "trial_moves_per_s": trials / dt,
+        "trials_per_update": trials / max(updates, 1),
         "kernel_ms": {"bin": prof["ms_bin"], "migrate": mig_ms, "check": prof["ms_check"],
                       "wall": dt * 1e3},
         "hbm_sweep": {"alg_bytes": phase_bytes + BIN_BYTES * w.n * passes,

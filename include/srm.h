@@ -275,6 +275,8 @@ typedef struct {
     int64_t checks;            /* global checks */
     double ms_migrate_main;    /* the colour phases' main kernels alone (no overflow launch) */
     int64_t main_kernels;      /* SRM_KERNEL_* bits of the main kernels that ran */
+    int64_t trials;            /* trial moves of every pass while counting is on: the
+                                  accepted trial's index, or N_l for a rejection */
 } srm_profile;
 
 /* Main migration kernel of a colour phase (srm_profile.main_kernels). */
@@ -283,7 +285,9 @@ typedef struct {
 #define SRM_KERNEL_CELL 4     /* one thread per cell (small grids) */
 #define SRM_KERNEL_PLATELET 8 /* platelets, one thread per cell */
 
-/* Switch profiling on (1) or off (0); resets the accumulated profile. */
+/* Profiling switches, reset with the accumulated profile: bit 0 times the
+ * phases above with hipEvents; bit 1 also counts trial moves (a small
+ * reduction over the accept codes after every pass, so it adds work). */
 srm_status srm_profile_enable(srm_ctx *ctx, int32_t on);
 /* Copy the accumulated profile (synchronises the stream). */
 srm_status srm_profile_read(srm_ctx *ctx, srm_profile *out);

@@ -56,7 +56,7 @@ class Profile(C.Structure):
     _fields_ = [("ms_bin", C.c_double), ("ms_migrate", C.c_double), ("ms_check", C.c_double),
                 ("bins", C.c_int64), ("launches_migrate", C.c_int64), ("passes", C.c_int64),
                 ("checks", C.c_int64), ("ms_migrate_main", C.c_double),
-                ("main_kernels", C.c_int64)]
+                ("main_kernels", C.c_int64), ("trials", C.c_int64)]
 
 
 class RunInfo(C.Structure):
@@ -298,10 +298,12 @@ class SRM:
         _check(lib().srm_last_acc(self._ctx, acc.ctypes.data_as(C.POINTER(C.c_uint8))))
         return acc
 
-    def profile(self, enable: Optional[bool] = None) -> dict:
-        """Read the device-time profile; enable=True/False (re)starts it."""
+    def profile(self, enable: Optional[bool] = None, trials: bool = False) -> dict:
+        """Read the device-time profile; enable=True/False (re)starts it
+        (trials=True also counts trial moves, which adds a reduction per
+        pass)."""
         if enable is not None:
-            _check(lib().srm_profile_enable(self._ctx, 1 if enable else 0))
+            _check(lib().srm_profile_enable(self._ctx, (1 if enable else 0) | (2 if trials else 0)))
         pr = Profile()
         _check(lib().srm_profile_read(self._ctx, C.byref(pr)))
         return {name: getattr(pr, name) for name, _ in Profile._fields_}

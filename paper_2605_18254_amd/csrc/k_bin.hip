@@ -34,8 +34,24 @@ __global__ void k_zero_counters(Counters *c)
     if (threadIdx.x == 0) {
         c->overlap = 0;
         c->bad = 0;
-        c->nfail = 0;
+        c->unused = 0;
     }
+}
+
+// Trials a pass ran: the accepted trial's index, or N_l for a rejection.
+__global__ void __launch_bounds__(kBlock) k_count_trials(const uint8_t *__restrict__ acc, int32_t n,
+                                                         int32_t n_l,
+                                                         unsigned long long *total)
+{
+    unsigned long long sum = 0;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int32_t c = acc[i];
+        sum += (unsigned long long)(c ? c : n_l);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if ((threadIdx.x & 63) == 0 && sum)
+        atomicAdd(total, sum);
 }
 
 __global__ void k_iota(int32_t *a, int32_t n)
@@ -286,6 +302,15 @@ hipError_t launch_fill_u8(uint8_t *a, int64_t n, uint8_t v, hipStream_t stream)
     unsigned nb = blocks_for(n);
     if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL(k_fill_u8, dim3(nb), dim3(kBlock), 0, stream, a, n, v);
+    return hipGetLastError();
+}
+
+hipError_t count_trials(const uint8_t *acc, int32_t n, int32_t n_l,
+                        unsigned long long *total, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const int32_t blocks = (n + kBlock - 1) / kBlock < 1024 ? (n + kBlock - 1) / kBlock : 1024;
+    hipLaunchKernelGGL(k_count_trials, dim3(blocks), dim3(kBlock), 0, stream, acc, n, n_l, total);
     return hipGetLastError();
 }
 

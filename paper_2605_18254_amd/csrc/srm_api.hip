@@ -59,6 +59,8 @@ struct srm_ctx {
     uint8_t *acc = nullptr;
     bool acc_valid = false;
     PBuf acc_buf{};          // storage order the acc codes refer to
+    bool count_trials_on = false;
+    unsigned long long *dtrials = nullptr;  // trial moves while profiling
     Counters *dcnt = nullptr;
     Counters *hcnt = nullptr;  // pinned
     double *dtmp = nullptr;    // 3n doubles: id-order staging
@@ -253,6 +255,7 @@ srm_status run_pass(srm_ctx *c, const PBuf &b, const Grid &g, double s, int kind
     }
     if (e0) c->release(e0);
     if (c->prof_on) c->prof.passes += 1;
+    if (c->count_trials_on) HIP_TRY(count_trials(c->acc, c->n, c->p.n_l, c->dtrials, c->stream));
     c->acc_valid = true;
     c->acc_buf = b;
     if (!want_check) return SRM_OK;
@@ -329,7 +332,8 @@ srm_status srm_init(const srm_params *p, const double *pos, const double *rho,
         (e = c->alloc(&c->sc.cell, n)) || (e = c->alloc(&c->sc.slot, n)) ||
         (e = c->alloc(&c->sc.tmpid, n)) ||
         (e = c->alloc(&c->acc, n)) || (e = c->alloc(&c->dtmp, 3 * n)) ||
-        (e = c->alloc(&c->itmp, n)) || (e = c->alloc(&c->dcnt, 1)))
+        (e = c->alloc(&c->itmp, n)) || (e = c->alloc(&c->dcnt, 1)) ||
+        (e = c->alloc(&c->dtrials, 1)))
         return bail(fail(SRM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
     {
         // tiles per colour phase are at most prod_a ceil((ncap / 2) / T)
@@ -780,7 +784,10 @@ srm_status srm_profile_enable(srm_ctx *c, int32_t on)
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->resolve();
     c->prof = srm_profile{};
-    c->prof_on = on != 0;
+    c->prof_on = (on & 1) != 0;
+    c->count_trials_on = (on & 2) != 0;
+    HIP_TRY(launch_fill_i32((int32_t *)c->dtrials, 2, 0, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
     return SRM_OK;
 }
 
@@ -789,6 +796,9 @@ srm_status srm_profile_read(srm_ctx *c, srm_profile *out)
     if (!c || !out) return fail(SRM_EINVAL, "NULL argument");
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->resolve();
+    unsigned long long trials = 0;
+    HIP_TRY(hipMemcpy(&trials, c->dtrials, sizeof(trials), hipMemcpyDeviceToHost));
+    c->prof.trials = (int64_t)trials;
     *out = c->prof;
     return SRM_OK;
 }

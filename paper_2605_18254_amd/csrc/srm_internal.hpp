@@ -23,7 +23,7 @@ struct PBuf {
 struct Counters {
     int32_t overlap;     // 1 if a colliding particle was found
     int32_t bad;         // 1 if an input coordinate was outside the box
-    int64_t nfail;       // unused by the check kernels (kept for layout)
+    int64_t unused;      // keeps the layout
     int32_t nfail_list;  // host copy of the failed-list length
     int32_t pad;
 };
@@ -49,6 +49,9 @@ struct ColourLattice {
 hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t stream);
 hipError_t launch_fill_u8(uint8_t *a, int64_t n, uint8_t v, hipStream_t stream);
 hipError_t launch_zero_counters(Counters *c, hipStream_t stream);
+// *total += sum over slots of (acc ? acc : n_l): the trials a pass ran.
+hipError_t count_trials(const uint8_t *acc, int32_t n, int32_t n_l,
+                        unsigned long long *total, hipStream_t stream);
 hipError_t launch_iota(int32_t *a, int32_t n, hipStream_t stream);
 
 // Counting sort of `src` by the cells of `g` into `dst` (Algorithm 2's
