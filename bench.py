@@ -144,9 +144,9 @@ def batched_extra(max_sweeps):
 
     ws = [srm_inputs.make_member(m) for m in srm_inputs.batch_members()]
     t0 = time.perf_counter()
-    shape = autotune(ws, sweeps=20, slots=(2, 4, 8), blocks=(64, 128, 256))
+    shape = autotune(ws, sweeps=40, slots=(2, 4, 8), blocks=(128,), wave_occupancy=(2, 3, 6))
     tune_s = time.perf_counter() - t0
-    _say(f"batch autotune -> slots={shape[0]} block={shape[1]} ({tune_s:.1f} s)")
+    _say(f"batch autotune -> slots={shape[0]} block={shape[1]} wave={shape[2]} ({tune_s:.1f} s)")
     b = Batch(ws)
     b.configure(*shape)
     torch.cuda.synchronize()
@@ -181,7 +181,8 @@ def batched_extra(max_sweeps):
         "max_sweeps": max_sweeps, "converged": info["converged"],
         "not_converged": info["not_converged"],
         "min_s_over_s_target": min(fr_b), "overlapping_pairs": overlaps,
-        "bitidentical_to_solo": identical, "launch": {"slots": shape[0], "block": shape[1]},
+        "bitidentical_to_solo": identical, "launch": {"slots": shape[0], "block": shape[1], "wave_occupancy": shape[2],
+                   "autotune_s": tune_s},
         "updates": info["updates"],
         "batched": {"s": dt_b, "updates_per_s": info["updates"] / dt_b,
                     "graph_replays": info["replays"]},

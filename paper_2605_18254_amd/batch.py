@@ -33,7 +33,7 @@ def _bind():
         return L
     vp, dp = C.c_void_p, C.POINTER(C.c_double)
     L.srm_batch_init.argtypes = [C.c_int32, C.POINTER(Params), dp, dp, C.POINTER(vp)]
-    L.srm_batch_configure.argtypes = [vp, C.c_int32, C.c_int32]
+    L.srm_batch_configure.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
     L.srm_batch_run.argtypes = [vp, C.c_int32, C.POINTER(BatchInfo)]
     L.srm_batch_get.argtypes = [vp, C.c_int32, dp, dp, C.POINTER(C.c_int64),
                                 C.POINTER(C.c_int64)]
@@ -81,8 +81,12 @@ class Batch:
                                  C.byref(ctx)))
         self._ctx = ctx
 
-    def configure(self, slots: int, block: int):
-        _bcheck(_bind().srm_batch_configure(self._ctx, int(slots), int(block)))
+    def configure(self, slots: int, block: int, wave_occupancy: int = 3):
+        """Schedule: pass slots per graph replay, threads per block of the
+        thread-per-cell kernels, and the occupancy from which a grid is
+        migrated with one wavefront per cell."""
+        _bcheck(_bind().srm_batch_configure(self._ctx, int(slots), int(block),
+                                            int(wave_occupancy)))
 
     def run(self, max_sweeps: int):
         info = BatchInfo()
@@ -113,11 +117,12 @@ class Batch:
 
 
 def autotune(workloads: Sequence, sweeps: int = 6, cache: Optional[str] = None,
-             slots=(1, 2, 4, 8), blocks=(64, 128, 256)):
-    """Time a few sweeps of the ensemble for each launch shape and return the
-    fastest (slots, block); results are cached by ensemble size in `cache`
-    (JSON).  Every shape gives bit-identical results, so the choice only
-    affects speed."""
+             slots=(1, 2, 4, 8), blocks=(64, 128, 256), wave_occupancy=(3,)):
+    """Time a few sweeps of the ensemble for each schedule (pass slots per
+    replay, block size, wavefront-per-cell occupancy threshold) and return
+    the fastest (slots, block, wave_occupancy); results are cached by
+    ensemble size in `cache` (JSON).  Every schedule gives bit-identical
+    results, so the choice only affects speed."""
     key = f"{len(workloads)}:{sum(w.n for w in workloads)}:" \
           f"{sum(w.n for w in workloads if w.dim == 3)}"
     if cache and os.path.exists(cache):
@@ -128,14 +133,15 @@ def autotune(workloads: Sequence, sweeps: int = 6, cache: Optional[str] = None,
     best, best_t = None, None
     for sl in slots:
         for bl in blocks:
-            b = Batch(workloads)
-            b.configure(sl, bl)
-            t0 = time.perf_counter()
-            b.run(sweeps)
-            dt = time.perf_counter() - t0
-            b.close()
-            if best_t is None or dt < best_t:
-                best, best_t = (sl, bl), dt
+            for wo in wave_occupancy:
+                b = Batch(workloads)
+                b.configure(sl, bl, wo)
+                t0 = time.perf_counter()
+                b.run(sweeps)
+                dt = time.perf_counter() - t0
+                b.close()
+                if best_t is None or dt < best_t:
+                    best, best_t = (sl, bl, wo), dt
     if cache:
         table = {}
         if os.path.exists(cache):

@@ -75,6 +75,7 @@ struct BatchDev {
     int32_t *failed;       // [0] count, then global slots
     int32_t *prefix;       // [4 classes (dim, wave)][8 colours][count + 1]
     int32_t *remaining;
+    int32_t wave_occ;      // mean particles per cell from which a grid is crowded
 };
 
 __device__ __forceinline__ PBuf set_buf(const BatchDev &d, int set)
@@ -142,7 +143,7 @@ __global__ void k_ctl_begin(BatchDev d)
         }
         int64_t ncell = 1;
         for (int ax = 0; ax < r.dim; ++ax) ncell *= r.g.na[ax];
-        r.wave = (int64_t)r.n >= (int64_t)kWaveOccupancy * ncell;
+        r.wave = (int64_t)r.n >= (int64_t)d.wave_occ * ncell;
         r.mode = kMain;
         r.k = 1;
     }
@@ -577,6 +578,7 @@ srm_status srm_batch_init(int32_t count, const srm_params *params, const double 
     h->poly = rho != nullptr;
     BatchDev &d = h->d;
     d.count = count;
+    d.wave_occ = kWaveOccupancy;
     d.ntotal = (int32_t)ntotal;
     d.ncells = (int32_t)ncells;
     hipError_t e = hipSuccess;
@@ -672,13 +674,16 @@ srm_status srm_batch_init(int32_t count, const srm_params *params, const double 
     return SRM_OK;
 }
 
-srm_status srm_batch_configure(srm_batch *b, int32_t slots_per_replay, int32_t block)
+srm_status srm_batch_configure(srm_batch *b, int32_t slots_per_replay, int32_t block,
+                               int32_t wave_occupancy)
 {
     if (!b || slots_per_replay < 1 || slots_per_replay > 64 ||
-        (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024))
+        (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024) ||
+        wave_occupancy < 1 || wave_occupancy > 64)
         return bfail(SRM_EINVAL, "bad configuration");
     b->h.slots = slots_per_replay;
     b->h.block = block;
+    b->h.d.wave_occ = wave_occupancy;
     if (b->h.exec) {
         (void)hipGraphExecDestroy(b->h.exec);
         b->h.exec = nullptr;

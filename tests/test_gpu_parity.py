@@ -464,14 +464,17 @@ def test_batch_launch_shape_invariance_and_notconv(srm):
     metas = srm_inputs.batch_members(count=6, n_scale=0.03, seed0=2000)
     ws = [srm_inputs.make_member(m) for m in metas]
     res = []
-    for slots, block in [(1, 64), (5, 256)]:
+    # schedules: every grid on one wavefront per cell, then (almost) every
+    # grid on one thread per cell
+    for slots, block, wave in [(1, 64, 1), (5, 256, 64), (3, 128, 3)]:
         b = Batch(ws)
-        b.configure(slots, block)
+        b.configure(slots, block, wave)
         st, info = b.run(10)           # stops early: not converged yet
         assert st == srm.ENOTCONV and info["not_converged"] == len(ws)
         st, info = b.run(600)          # continues to the target
         assert st == 0
         res.append([b.get(r)[0] for r in range(len(ws))])
         b.close()
-    for a_, b_ in zip(*res):
-        assert np.array_equal(a_, b_)
+    for other in res[1:]:
+        for a_, b_ in zip(res[0], other):
+            assert np.array_equal(a_, b_)
