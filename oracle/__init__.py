@@ -98,13 +98,15 @@ def lib():
         L.o_rdf_brute.argtypes = [C.POINTER(State), C.c_int32, C.c_double,
                                   C.POINTER(C.c_uint64)]
         L.o_nearest_brute.argtypes = [C.POINTER(State), C.c_double, dp]
+        L.o_percolation.argtypes = [C.POINTER(State), C.c_double, C.c_double,
+                                    C.POINTER(C.c_int32)]
         L.o_disks_intersect.argtypes = [dp, dp, C.c_double, dp, dp, C.c_double, dp]
         L.o_softrdf_fwd.argtypes = [C.POINTER(SoftParams), C.c_int64, dp, dp, dp, dp]
         L.o_softrdf_grad.argtypes = [C.POINTER(SoftParams), C.c_int64, dp, dp, dp, C.c_double,
                                      dp, dp]
         L.o_disks_intersect.restype = C.c_int
         for f in ("o_pass", "o_overlap", "o_sweep", "o_run", "o_rdf_brute", "o_bin",
-                  "o_nearest_brute"):
+                  "o_nearest_brute", "o_percolation"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -321,6 +323,26 @@ class Oracle:
         dist = np.empty(self.n, dtype=np.float64)
         _check(lib().o_nearest_brute(C.byref(self.st), float(r_max), _dp(dist)))
         return dist
+
+    def percolation(self, gap: float, s=None) -> int:
+        """Axes (bit mask) along which a cluster of particles grown by `gap`
+        wraps around the box, at radius scale s (default: the state's)."""
+        m = C.c_int32()
+        _check(lib().o_percolation(C.byref(self.st), float(self.s if s is None else s),
+                                   float(gap), C.byref(m)))
+        return m.value
+
+    def critical_gap(self, lo: float, hi: float, iters: int = 40) -> float:
+        """Bisection on the gap, as the library does it: lo must not
+        percolate and hi must; returns the final hi."""
+        assert not self.percolation(lo) and self.percolation(hi)
+        for _ in range(iters):
+            mid = 0.5 * (lo + hi)
+            if self.percolation(mid):
+                hi = mid
+            else:
+                lo = mid
+        return hi
 
     def soa(self) -> np.ndarray:
         return np.ascontiguousarray(self.pos[:, : self.dim].T)

@@ -622,6 +622,87 @@ int64_t o_pairs_brute(const o_state *st, double s, double gap, int64_t cap, int3
     return cnt;
 }
 
+/* Hard core - soft shell percolation (Sec. 3.3): particles are bonded when
+ * they overlap after growing by `gap` (the o_pairs_brute predicate); a
+ * cluster percolates along axis a when it wraps around the periodic box
+ * along a.  Union-find in which every particle keeps its periodic image
+ * relative to its parent: a bond i-j whose nearest image of j is x_j + s L
+ * (s_a = +1 when x_j - x_i < -L_a/2, -1 when > L_a/2) either merges two
+ * clusters with the implied relative image, or closes a cycle, which winds
+ * along the axes where the images disagree.  *mask = OR of those axes. */
+static int64_t o_uf_find(int64_t *parent, int32_t (*off)[3], int64_t i, int32_t out[3])
+{
+    int32_t acc[3] = {0, 0, 0};
+    int64_t r = i;
+    while (parent[r] != r) {
+        for (int a = 0; a < 3; ++a) acc[a] += off[r][a];
+        r = parent[r];
+    }
+    /* path compression: point i (and its chain) at the root */
+    int64_t k = i;
+    int32_t rem[3] = {acc[0], acc[1], acc[2]};
+    while (parent[k] != k) {
+        int64_t next = parent[k];
+        int32_t step[3] = {off[k][0], off[k][1], off[k][2]};
+        parent[k] = r;
+        for (int a = 0; a < 3; ++a) {
+            off[k][a] = rem[a];
+            rem[a] -= step[a];
+        }
+        k = next;
+    }
+    for (int a = 0; a < 3; ++a) out[a] = acc[a];
+    return r;
+}
+
+int o_percolation(const o_state *st, double s, double gap, int32_t *mask)
+{
+    const o_params *p = &st->p;
+    int64_t n = p->n;
+    int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int32_t (*off)[3] = (int32_t (*)[3])malloc(sizeof(int32_t) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!parent || !off) { free(parent); free(off); return O_ENOMEM; }
+    for (int64_t i = 0; i < n; ++i) {
+        parent[i] = i;
+        off[i][0] = off[i][1] = off[i][2] = 0;
+    }
+    *mask = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = i + 1; j < n; ++j) {
+            int hit;
+            if (p->shape == O_PLATELET) {
+                double ai = o_radius(st, s, i) + 0.5 * gap, aj = o_radius(st, s, j) + 0.5 * gap;
+                hit = o_disks_intersect(&st->pos[3 * i], &st->nrm[3 * i], ai,
+                                        &st->pos[3 * j], &st->nrm[3 * j], aj, p->box);
+            } else {
+                double sig = (o_radius(st, s, i) + o_radius(st, s, j)) + gap;
+                hit = o_pair_q(st, i, j) <= sig * sig;
+            }
+            if (!hit) continue;
+            int32_t sh[3] = {0, 0, 0};
+            for (int a = 0; a < p->dim; ++a) {
+                double d = st->pos[3 * j + a] - st->pos[3 * i + a];
+                sh[a] = (d > 0.5 * p->box[a]) ? -1 : ((d < -0.5 * p->box[a]) ? 1 : 0);
+            }
+            /* image of i relative to its root oi, of j relative to its root oj;
+             * the bond says image(j) = image(i) + sh */
+            int32_t oi[3], oj[3];
+            int64_t ri = o_uf_find(parent, off, i, oi);
+            int64_t rj = o_uf_find(parent, off, j, oj);
+            if (ri != rj) {
+                parent[rj] = ri;
+                for (int a = 0; a < 3; ++a) off[rj][a] = oi[a] + sh[a] - oj[a];
+            } else {
+                for (int a = 0; a < 3; ++a)
+                    if (oi[a] + sh[a] != oj[a]) *mask |= 1 << a;
+            }
+        }
+    }
+    free(parent);
+    free(off);
+    return O_OK;
+}
+
 /* Histogram of centre distances r_ij (i<j): bin b = (int)(r * (nbins / r_max)),
  * counted when b < nbins. */
 int o_rdf_brute(const o_state *st, int32_t nbins, double r_max, uint64_t *counts)

@@ -223,3 +223,69 @@ def test_nearest_matches_a_kd_tree(oracle_lib, dim):
     clear = np.abs(ref - med) > 1e-12 * med
     assert np.array_equal(np.isinf(d_small)[clear], (ref >= med)[clear])
     assert np.array_equal(d_small[~np.isinf(d_small)], d[~np.isinf(d_small)])
+
+
+# ------------------------------------------------------------ percolation
+
+def _balls(oracle_lib, pos, s):
+    dim, n = pos.shape
+    return oracle_lib.Oracle(dim=dim, n=n, s_target=s, c_w=0.01, c_m=0.1 * s, n_k=8, n_l=8,
+                             seed=1, pos=pos, s0=s)
+
+
+def test_percolation_of_chains_and_rings(oracle_lib):
+    """A chain of balls 0.1 apart along x wraps along x once the gap closes
+    the 0.02 surface gaps (0.1 - 2 * 0.04), and only along x; a lattice of
+    such chains in 2D wraps along both axes; a closed ring inside the box
+    never percolates."""
+    x = (np.arange(10) + 0.5) / 10
+    chain = np.stack([x, np.full(10, 0.3), np.full(10, 0.6)])
+    o = _balls(oracle_lib, chain, 0.04)
+    assert o.percolation(0.0) == 0
+    assert o.percolation(0.019) == 0
+    assert o.percolation(0.021) == 1
+    gc = o.critical_gap(0.0, 0.05, iters=40)
+    assert abs(gc - 0.02) < 1e-10
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    grid = np.stack([X.ravel(), Y.ravel()])
+    o2 = _balls(oracle_lib, grid, 0.04)
+    assert o2.percolation(0.019) == 0 and o2.percolation(0.021) == 3
+    t = np.linspace(0, 2 * np.pi, 24, endpoint=False)
+    ring = np.stack([0.5 + 0.2 * np.cos(t), 0.5 + 0.2 * np.sin(t)])
+    o3 = _balls(oracle_lib, ring, 0.02)
+    assert o3.percolation(0.03) == 0  # neighbours bonded: a ring, no winding
+    assert len(o3.pairs_brute(0.03)) >= 24
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_percolation_matches_a_doubled_box(oracle_lib, dim):
+    """Random balls: a cluster wraps along axis a exactly when, in the box
+    doubled along every axis (2^dim copies, minimum image in the doubled
+    box), some particle is connected to its own copy shifted by L along a
+    (scipy k-d tree bonds and connected components: another algorithm)."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(21 + dim)
+    n = 700 if dim == 2 else 900
+    pos = rng.random((dim, n))
+    r = 0.012 if dim == 2 else 0.03
+    o = _balls(oracle_lib, pos, r)
+    shifts = np.array(np.meshgrid(*[[0, 1]] * dim, indexing="ij")).reshape(dim, -1).T
+    big = np.concatenate([pos.T + sh for sh in shifts])          # (2^dim n, dim) in [0, 2)
+    tree = cKDTree(big, boxsize=2.0)
+    seen = set()
+    for gap in np.linspace(0.0, 3.0 * r, 13):
+        pairs = tree.query_pairs(2 * r + gap, output_type="ndarray")
+        m = len(big)
+        adj = coo_matrix((np.ones(len(pairs)), (pairs[:, 0], pairs[:, 1])), shape=(m, m))
+        _, lab = connected_components(adj, directed=False)
+        ref = 0
+        for a in range(dim):
+            img = np.nonzero(np.all(shifts == np.eye(dim, dtype=int)[a], axis=1))[0][0]
+            if np.any(lab[:n] == lab[img * n: img * n + n]):
+                ref |= 1 << a
+        got = o.percolation(gap)
+        assert got == ref, (gap, got, ref)
+        seen.add(got)
+    assert 0 in seen and (2 ** dim - 1) in seen   # both regimes covered
