@@ -188,6 +188,21 @@ srm_status srm_last_acc(srm_ctx *ctx, uint8_t *acc_by_id);
 srm_status srm_nearest(srm_ctx *ctx, double r_max, double *dist_by_id, int32_t nbins,
                        uint64_t *hist);
 
+/* Hard core - soft shell percolation (the critical percolation distance of
+ * Sec. 3.3, Fig. 9): particles are bonded when they overlap after growing
+ * by `gap` (the srm_pairs predicate: (R_i + R_j) + gap for balls, disk
+ * radii a + gap/2 for platelets), and *wraps gets bit a set when a cluster
+ * wraps around the periodic box along axis a (a cycle of bonds whose
+ * periodic images do not close along a); 0 means no cluster spans the box.
+ * Needs 2 R_max + gap <= L/2.  Errors: SRM_EINVAL; SRM_ECAPACITY if a
+ * cluster's image offsets exceed +-510 boxes. */
+srm_status srm_percolation(srm_ctx *ctx, double gap, int32_t *wraps);
+/* Critical percolation distance by bisection on the gap: lo must not
+ * percolate and hi must; after `iters` halvings (mid = (lo + hi) / 2, 0 to
+ * 200 of them) *gap_c is the final hi, the smallest percolating gap found.
+ * Errors: SRM_EINVAL. */
+srm_status srm_critical_gap(srm_ctx *ctx, double lo, double hi, int32_t iters, double *gap_c);
+
 /* ---- differentiable descriptor: soft g(r) + overlap energy -------------- */
 
 /* A workspace for configurations of n particles in a fixed periodic box.

@@ -25,6 +25,7 @@ MAIN, SHAKE = 0, 1
 OK, EINVAL, ENOMEM, EDEVICE, EOVERLAP, ENOTCONV, ECAPACITY = 0, -1, -2, -3, -4, -5, -6
 
 SYMBOLS = ["srm_init", "srm_sweep", "srm_run_to_fraction", "srm_pairs", "srm_rdf", "srm_nearest",
+           "srm_percolation", "srm_critical_gap",
            "srm_get_state", "srm_free", "srm_last_error", "srm_grid", "srm_cells", "srm_pass",
            "srm_last_acc", "srm_set_state", "srm_softrdf_create", "srm_softrdf_forward",
            "srm_softrdf_backward", "srm_softrdf_free", "srm_profile_enable", "srm_profile_read",
@@ -91,6 +92,8 @@ def lib():
     L.srm_pairs.argtypes = [vp, C.c_double, C.c_int64, vp, C.POINTER(C.c_int64), C.c_int32]
     L.srm_rdf.argtypes = [vp, C.c_int32, C.c_double, C.POINTER(C.c_uint64), dp]
     L.srm_nearest.argtypes = [vp, C.c_double, dp, C.c_int32, C.POINTER(C.c_uint64)]
+    L.srm_percolation.argtypes = [vp, C.c_double, C.POINTER(C.c_int32)]
+    L.srm_critical_gap.argtypes = [vp, C.c_double, C.c_double, C.c_int32, dp]
     L.srm_get_state.argtypes = [vp, vp, vp, dp, C.POINTER(C.c_int64), C.c_int32]
     L.srm_free.argtypes = [vp]
     L.srm_last_error.argtypes = []
@@ -330,6 +333,20 @@ class SRM:
                                  hist.ctypes.data_as(C.POINTER(C.c_uint64)) if nbins > 0
                                  else None))
         return dist, (hist if nbins > 0 else None)
+
+    def percolation(self, gap: float) -> int:
+        """Bit a set when a cluster of particles grown by `gap` wraps around
+        the box along axis a."""
+        m = C.c_int32()
+        _check(lib().srm_percolation(self._ctx, float(gap), C.byref(m)))
+        return m.value
+
+    def critical_gap(self, lo: float, hi: float, iters: int = 40) -> float:
+        """Smallest percolating gap found by bisection between lo (not
+        percolating) and hi (percolating)."""
+        out = C.c_double()
+        _check(lib().srm_critical_gap(self._ctx, float(lo), float(hi), int(iters), C.byref(out)))
+        return out.value
 
     def rdf(self, nbins: int, r_max: float):
         counts = np.zeros(nbins, dtype=np.uint64)

@@ -625,7 +625,7 @@ namespace {
 
 // Device staging for the diagnostics: copy host inputs in, run, copy out.
 struct DevArena {
-    void *p[4] = {nullptr, nullptr, nullptr, nullptr};
+    void *p[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     ~DevArena()
     {
         for (void *q : p)
@@ -745,6 +745,99 @@ srm_status srm_rdf(srm_ctx *c, int32_t nbins, double r_max, uint64_t *counts, do
             g_out[b] = ideal > 0.0 ? (double)counts[b] / ideal : 0.0;
         }
     }
+    return SRM_OK;
+}
+
+namespace {
+
+// Wrapping axes (bit a) of the clusters of particles that overlap after
+// growing by `gap`.
+srm_status percolation_mask(srm_ctx *c, double gap, int32_t *mask)
+{
+    srm_status st = ensure_rows(c);
+    if (st) return st;
+    const double reach = 2.0 * (c->s * c->rho_max) + gap;
+    const Grid g = cutoff_grid(c, reach);
+    if ((st = bin(c, c->P, c->T, g))) return st;
+    HIP_TRY(pairs_count(c->dim, c->T, c->sc.start, g, c->n, c->p.shape, c->s, gap, c->rowcnt,
+                        c->stream));
+    HIP_TRY(scan_counts(c->rowcnt, c->rowoff, c->sc.partials, c->n, c->stream));
+    int32_t total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, c->rowoff + c->n, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *mask = 0;
+    if (total == 0) return SRM_OK;
+    DevArena d;
+    HIP_TRY(hipMalloc(&d.p[0], (size_t)total * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&d.p[1], (size_t)total * 2 * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&d.p[2], (size_t)total * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&d.p[3], (size_t)c->n * sizeof(unsigned long long)));
+    HIP_TRY(hipMalloc(&d.p[4], 4 * sizeof(int32_t)));
+    int32_t *ij = (int32_t *)d.p[1], *shift = (int32_t *)d.p[2], *flags = (int32_t *)d.p[4];
+    auto *state = (unsigned long long *)d.p[3];
+    HIP_TRY(pairs_emit(c->dim, c->T, c->sc.start, g, c->n, c->p.shape, c->s, gap, c->rowoff,
+                       (int32_t *)d.p[0], ij, c->stream));
+    const double *xs[3] = {c->P.x[0], c->P.x[1], c->P.x[2]};
+    HIP_TRY(to_id_order(xs, c->dim, c->P.id, c->n, c->dtmp, c->stream));
+    HIP_TRY(bond_shifts(ij, total, c->dtmp, c->n, c->dim, g, shift, c->stream));
+    HIP_TRY(perc_init(state, c->n, c->stream));
+    HIP_TRY(launch_fill_i32(flags, 4, 0, c->stream));
+    int32_t host[4] = {0, 0, 0, 0};
+    // each round moves every cluster's smallest label at least one bond further
+    for (int64_t round = 0;; ++round) {
+        if (round > (int64_t)c->n + 1) return fail(SRM_EDEVICE, "percolation labels did not settle");
+        HIP_TRY(launch_fill_i32(flags, 1, 0, c->stream));
+        HIP_TRY(perc_relax(ij, shift, total, state, flags, c->stream));
+        HIP_TRY(hipMemcpyAsync(host, flags, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        if (host[1]) return fail(SRM_ECAPACITY, "cluster image offsets exceed the packed range");
+        if (!host[0]) break;
+    }
+    HIP_TRY(perc_check(ij, shift, total, state, flags, c->stream));
+    HIP_TRY(hipMemcpyAsync(host, flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *mask = host[2];
+    return SRM_OK;
+}
+
+srm_status check_gap(const srm_ctx *c, double gap)
+{
+    if (!(gap >= 0.0) || !isfinite(gap)) return fail(SRM_EINVAL, "gap must be finite and >= 0");
+    double lmin = c->p.box[0];
+    for (int a = 1; a < c->dim; ++a) lmin = c->p.box[a] < lmin ? c->p.box[a] : lmin;
+    if (!(2.0 * (c->s * c->rho_max) + gap <= 0.5 * lmin))
+        return fail(SRM_EINVAL, "2 R_max + gap must not exceed half the box");
+    return SRM_OK;
+}
+
+}  // namespace
+
+srm_status srm_percolation(srm_ctx *c, double gap, int32_t *wraps)
+{
+    if (!c || !wraps) return fail(SRM_EINVAL, "NULL argument");
+    srm_status st = check_gap(c, gap);
+    if (st) return st;
+    return percolation_mask(c, gap, wraps);
+}
+
+srm_status srm_critical_gap(srm_ctx *c, double lo, double hi, int32_t iters, double *gap_c)
+{
+    if (!c || !gap_c) return fail(SRM_EINVAL, "NULL argument");
+    if (iters < 0 || iters > 200 || !(lo < hi)) return fail(SRM_EINVAL, "need lo < hi, 0 <= iters <= 200");
+    srm_status st;
+    if ((st = check_gap(c, lo)) || (st = check_gap(c, hi))) return st;
+    int32_t m_lo = 0, m_hi = 0;
+    if ((st = percolation_mask(c, lo, &m_lo)) || (st = percolation_mask(c, hi, &m_hi))) return st;
+    if (m_lo || !m_hi) return fail(SRM_EINVAL, "lo must not percolate and hi must");
+    for (int32_t k = 0; k < iters; ++k) {
+        const double mid = 0.5 * (lo + hi);
+        int32_t m = 0;
+        if ((st = percolation_mask(c, mid, &m))) return st;
+        if (m) hi = mid;
+        else lo = mid;
+    }
+    *gap_c = hi;
     return SRM_OK;
 }
 

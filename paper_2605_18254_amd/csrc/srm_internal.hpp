@@ -107,6 +107,16 @@ hipError_t pairs_emit(int dim, const PBuf &b, const int32_t *start, const Grid &
                       int32_t *ij, hipStream_t stream);
 hipError_t rdf_counts(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
                       int32_t nbins, double inv, unsigned long long *counts, hipStream_t stream);
+// Percolation (k_perc.hip): bond image shifts, (label, offset) relaxation
+// until flags[0] stays 0 (flags[1]: offset overflow), then the wrapping axes
+// OR-ed into flags[2].
+hipError_t bond_shifts(const int32_t *ij, int64_t nb, const double *pos_by_id, int32_t n, int dim,
+                       const Grid &g, int32_t *shift, hipStream_t stream);
+hipError_t perc_init(unsigned long long *state, int32_t n, hipStream_t stream);
+hipError_t perc_relax(const int32_t *ij, const int32_t *shift, int64_t nb,
+                      unsigned long long *state, int32_t *flags, hipStream_t stream);
+hipError_t perc_check(const int32_t *ij, const int32_t *shift, int64_t nb,
+                      const unsigned long long *state, int32_t *flags, hipStream_t stream);
 // Nearest-neighbour distance (by id, nullable) and its histogram (nullable)
 // for every particle, searched within r_max (grid cells >= r_max).
 hipError_t nearest(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,

@@ -429,6 +429,51 @@ def test_nearest_edge_cases_and_errors(srm, oracle_lib):
     gp.close()
 
 
+@pytest.mark.parametrize("kind", ["disks", "spheres", "platelets"])
+def test_percolation_matches_oracle(srm, oracle_lib, kind):
+    """Wrapping axes of the gap-grown clusters at a ladder of gaps, and the
+    critical gap found by 30 bisection steps, equal the oracle's union-find
+    (same bonds bit for bit, so the same masks and the same bisection)."""
+    if kind == "platelets":
+        w = srm_inputs.make("platelets", n=1500, seed=7, f_target=0.02)
+        steps = 40
+    else:
+        w = _mk(2 if kind == "disks" else 3, 2500, 161, 0.45 if kind == "disks" else 0.3)
+        steps = 3000
+    o = oracle_lib.Oracle.from_workload(w)
+    o.run(steps)
+    g = _gpu_from_oracle(srm, o, w)
+    r = o.s
+    lo, hi = 0.0, 3.0 * r
+    masks = []
+    for gap in np.linspace(lo, hi, 9):
+        mg, mo = g.percolation(gap), o.percolation(gap)
+        assert mg == mo, (gap, mg, mo)
+        masks.append(mo)
+    _say(f"percolation {kind}: masks {masks}")
+    if masks[0] == 0 and masks[-1] != 0:
+        gc_g = g.critical_gap(lo, hi, 30)
+        gc_o = o.critical_gap(lo, hi, 30)
+        assert gc_g == gc_o
+        _say(f"percolation {kind}: critical gap {gc_g / r:.6f} r")
+    g.close()
+
+
+def test_percolation_chain_and_errors(srm):
+    """A chain of balls 0.1 apart percolates along x from a gap of 0.02
+    (critical gap to 1e-10); a gap beyond half the box is rejected."""
+    x = (np.arange(10) + 0.5) / 10
+    chain = np.stack([x, np.full(10, 0.3), np.full(10, 0.6)])
+    g = srm.SRM(dim=3, n=10, s_target=0.04, c_w=0.01, c_m=0.004, n_k=8, n_l=8, seed=1,
+                pos=chain, s0=0.04)
+    assert g.percolation(0.019) == 0 and g.percolation(0.021) == 1
+    assert abs(g.critical_gap(0.0, 0.05, 40) - 0.02) < 1e-10
+    with pytest.raises(srm.SrmError) as e:
+        g.percolation(0.45)
+    assert e.value.status == srm.EINVAL
+    g.close()
+
+
 # ------------------------------------------------------------ batched RVEs
 
 def test_batch_members_bitidentical_to_solo_runs(srm, oracle_lib):
