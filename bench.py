@@ -211,10 +211,22 @@ def platelet_extra(max_sweeps):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         overlaps = len(g.pairs(0.0))
+        # critical percolation distance of the final state (bisection on the
+        # tunnelling gap, 30 halvings), in platelet diameters
+        diam = 2.0 * w.s_target
+        hi = 0.25 * diam
+        while not g.percolation(hi) and hi < 8 * diam:
+            hi *= 2.0
+        t1 = time.perf_counter()
+        gap_c = g.critical_gap(0.0, hi, 30) if g.percolation(hi) else None
+        dt_perc = time.perf_counter() - t1
         g.close()
         out[tag] = {"converged": st == 0, "sweeps": info["sweeps"], "passes": info["passes"],
                     "s": dt, "updates_per_s": info["updates"] / dt,
-                    "fraction": info["fraction"], "overlapping_pairs": overlaps}
+                    "fraction": info["fraction"], "overlapping_pairs": overlaps,
+                    "number_density": w.n * diam ** 3,
+                    "critical_gap_over_d": None if gap_c is None else gap_c / diam,
+                    "critical_gap_s": dt_perc}
         _say(f"platelets {tag}: {out[tag]}")
     out["workload"] = ("platelets N=2e5, thickness D/100, f_target=0.02, seed 2, c_w=0.01, "
                        "c_m=0.1*s_target, c_n=c_m/a_t, N_k=N_l=8")
