@@ -269,6 +269,62 @@ def n_scaling_extra():
     return {"workload": "spheres3d, unit cube, f 0.35, seed 1, uniform start at s = 0",
             "runs": rows, "time_exponent_n_ge_1e5": slope}
 
+def platelet_protocol_extra(densities=(1.0, 2.0, 5.0), n=20_000, relax_sweeps=100):
+    """The paper's platelet application (Sec. 3.3, Figs. 8-9): 20000 platelets
+    (aspect ratio 100) at number density rho = N D^3 / L^3, grown with a
+    larger swelling rate (c_w = 0.02, twice the default, with c_m = 0.1 a_t;
+    smaller migration steps jam the run far below the target), then relaxed
+    with zero swelling
+    and a large migration step (c_m = 0.5 a_t) for `relax_sweeps` sweeps;
+    the critical percolation distance delta_c / D of both states (30
+    bisection steps on the tunnelling gap)."""
+    import math
+
+    import torch
+
+    import paper_2605_18254_amd as srm
+    import srm_inputs
+
+    def gap_c(g, diam):
+        hi = 0.05 * diam
+        while not g.percolation(hi) and hi < 8 * diam:
+            hi *= 2.0
+        return g.critical_gap(0.0, hi, 30) / diam if g.percolation(hi) else None
+
+    rows = []
+    for rho in densities:
+        f = math.pi * rho / 400.0  # N pi (D/2)^2 (D/100) / L^3
+        w = srm_inputs.make("platelets", n=n, seed=11, f_target=f, c_w=0.02, c_m_rel=0.1)
+        diam = 2.0 * w.s_target
+        g = srm.SRM.from_workload(w, device=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = g.run(2000)
+        torch.cuda.synchronize()
+        t_hoc = time.perf_counter() - t0
+        hoc = gap_c(g, diam)
+        pos, nrm, s_fin, t_fin = g.state()
+        g.close()
+        c_m = 0.5 * w.s_target
+        r = srm.SRM(dim=3, n=n, s_target=w.s_target, c_w=0.0, c_m=c_m, n_k=8, n_l=8,
+                    seed=w.seed, pos=pos, normals=nrm, shape=srm.PLATELET, c_n=c_m / w.s_target,
+                    thick_ratio=w.thick_ratio, s0=s_fin, sweep0=t_fin)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(relax_sweeps):
+            r.sweep()
+        torch.cuda.synchronize()
+        t_rel = time.perf_counter() - t0
+        rel = gap_c(r, diam)
+        overlaps = len(r.pairs(0.0))
+        r.close()
+        rows.append({"rho": rho, "f": f, "converged": st == 0, "grow_sweeps": info["sweeps"],
+                     "grow_s": t_hoc, "relax_s": t_rel, "delta_c_over_d_grown": hoc,
+                     "delta_c_over_d_relaxed": rel, "overlapping_pairs": overlaps})
+        _say(f"platelet protocol: {rows[-1]}")
+    return {"workload": f"{n} platelets, aspect ratio 100, seed 11; grown: c_w 0.02, c_m 0.1 a_t; "
+                        f"relax: c_w 0, c_m 0.5 a_t, {relax_sweeps} sweeps", "runs": rows}
+
 def grad_extra(steps, steer_steps):
     """Soft g(r) (64 Gaussian bins up to 5r) + overlap energy, forward and
     hand-written backward, on N = 2e5 spheres grown by SRM to f = 0.30; then
@@ -458,6 +514,7 @@ def main():
     if not args.no_extras:
         out["extras"] = {"n_scaling": n_scaling_extra(),
                          "platelets": platelet_extra(3000),
+                         "platelet_protocol": platelet_protocol_extra(),
                          "batched": batched_extra(args.batch_sweeps),
                          "gradient": grad_extra(20, 10)}
     if not args.no_cpu_baseline:
