@@ -80,6 +80,8 @@ def uniform_points(n: int, dim: int, seed: int, box=(1.0, 1.0, 1.0)) -> np.ndarr
     pos = np.empty((dim, n), dtype=np.float64)
     for a in range(dim):
         pos[a] = u[:, a] * float(box[a])
+        # u < 1, but u * L can round up to L itself: keep the box half-open
+        pos[a] = np.where(pos[a] >= box[a], np.nextafter(float(box[a]), 0.0), pos[a])
     return pos
 
 

@@ -198,10 +198,16 @@ def _unit(o, i, kind, k, l):
     return oracle.unitvec(o.dim, o.params.seed, int(i), o.t, kind, k, l, 0, o.params.c_m)
 
 
-@pytest.mark.parametrize("dim,n,f,cw_mult", [(2, 300, 0.45, 1.0), (3, 300, 0.3, 1.0),
-                                             (2, 12, 0.3, 1.0), (3, 700, 0.4, 3.0)])
-def test_pass_equals_bruteforce_replay(oracle_lib, dim, n, f, cw_mult):
-    w = _mk(dim, n, 21 + dim, f=f, c_w=0.01 * cw_mult)
+@pytest.mark.parametrize("dim,n,f,cw_mult,box", [(2, 300, 0.45, 1.0, (1.0, 1.0)),
+                                                 (3, 300, 0.3, 1.0, (1.0, 1.0, 1.0)),
+                                                 (2, 12, 0.3, 1.0, (1.0, 1.0)),
+                                                 (3, 700, 0.4, 3.0, (1.0, 1.0, 1.0)),
+                                                 (2, 400, 0.45, 1.0, (1.0, 0.55)),
+                                                 (3, 600, 0.35, 1.0, (0.8, 1.0, 1.4))])
+def test_pass_equals_bruteforce_replay(oracle_lib, dim, n, f, cw_mult, box):
+    """One pass replayed particle by particle in the schedule order with
+    all-pairs tests, in square and in stretched boxes."""
+    w = _mk(dim, n, 21 + dim, f=f, c_w=0.01 * cw_mult, box=box)
     o = oracle_lib.Oracle.from_workload(w)
     # bring it to a dense, admissible state first
     rc, _, _ = o.run(2000)
