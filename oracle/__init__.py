@@ -105,6 +105,11 @@ def lib():
         L.o_softrdf_grad.argtypes = [C.POINTER(SoftParams), C.c_int64, dp, dp, dp, C.c_double,
                                      dp, dp]
         L.o_disks_intersect.restype = C.c_int
+        L.o_rsa_candidate.argtypes = [C.c_int, C.c_int, dp, C.c_uint64, C.c_uint64, dp, dp]
+        L.o_rsa.argtypes = [C.c_int, C.c_int, C.c_int64, dp, C.c_double, C.c_uint64,
+                            C.c_int64, dp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                            C.POINTER(C.c_int64)]
+        L.o_rsa.restype = C.c_int
         for f in ("o_pass", "o_overlap", "o_sweep", "o_run", "o_rdf_brute", "o_bin",
                   "o_nearest_brute", "o_percolation"):
             getattr(L, f).restype = C.c_int
@@ -131,6 +136,40 @@ def unitvec(dim, seed, pid, t, kind, k, l, stream, length):
     v = np.zeros(3)
     r = lib().o_unitvec(dim, seed, pid, t, kind, k, l, stream, length, _dp(v))
     return v, r
+
+
+def rsa_candidates(dim, shape, box, seed, ks):
+    """Centres (len(ks), 3) and normals (len(ks), 3; zeros for balls) of the
+    RSA stream's candidates ks."""
+    box3 = np.array(tuple(box) + (1.0,) * (3 - len(box)), dtype=np.float64)
+    ks = np.asarray(ks, dtype=np.int64)
+    x = np.zeros((len(ks), 3))
+    m = np.zeros((len(ks), 3))
+    xi, mi = np.zeros(3), np.zeros(3)
+    for r, k in enumerate(ks):
+        lib().o_rsa_candidate(dim, shape, _dp(box3), seed, int(k), _dp(xi), _dp(mi))
+        x[r], m[r] = xi, mi
+    return x, m
+
+
+def rsa(dim, shape, n, box, radius, seed, max_candidates=None):
+    """Classical RSA of n equal particles.  Returns (status, pos (dim, n) SoA,
+    normals (n, 3) or None, src (candidate index per particle), drawn,
+    placed); on ENOTCONV only the first `placed` particles are valid."""
+    box3 = np.array(tuple(box) + (1.0,) * (3 - len(box)), dtype=np.float64)
+    if max_candidates is None:
+        max_candidates = 1000 * max(n, 1)
+    pos = np.zeros((max(n, 1), 3))
+    nrm = np.zeros((max(n, 1), 3)) if shape == 1 else None
+    src = np.zeros(max(n, 1), dtype=np.int64)
+    drawn, placed = C.c_int64(), C.c_int64()
+    rc = lib().o_rsa(dim, shape, n, _dp(box3), float(radius), seed, int(max_candidates),
+                     _dp(pos), _dp(nrm), src.ctypes.data_as(C.POINTER(C.c_int64)),
+                     C.byref(drawn), C.byref(placed))
+    if rc not in (OK, ENOTCONV):
+        _check(rc)
+    soa = np.ascontiguousarray(pos[:n, :dim].T)
+    return rc, soa, (nrm[:n] if nrm is not None else None), src[:n], drawn.value, placed.value
 
 
 def disks_intersect(c1, n1, a1, c2, n2, a2, box=(1.0, 1.0, 1.0)) -> bool:

@@ -43,6 +43,12 @@
  *    exact disk-disk intersection (chords on the planes' common line); the
  *    centre trial and a normal trial (stream 1, step c_n) are accepted or
  *    rejected together.
+ *  - initial configuration (Sec. 2, Alg. 1 "RSA procedure"): classical random
+ *    sequential addition of equal particles.  One stream of candidates
+ *    k = 0, 1, 2, ... (Philox counters (k_lo, k_hi, call, 2) for the centre,
+ *    (k_lo, k_hi, call, 3) for a platelet's normal); a candidate is kept when
+ *    it meets none of the particles kept before it (the contact test of
+ *    Alg. 5, touching counts) and gets the next particle id.
  */
 #include <math.h>
 
@@ -575,6 +581,100 @@ int o_run(o_state *st, int32_t max_sweeps, int64_t *sweeps_out, int64_t *passes_
     }
     if (sweeps_out) *sweeps_out = sweeps;
     if (passes_out) *passes_out = passes;
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Random sequential addition (Sec. 2: the non-overlapping start at f0). */
+/* ------------------------------------------------------------------ */
+/* 53-bit uniform in [0, 1) from two words: the top 27 bits of the first and
+ * the top 26 of the second, ((w_a >> 5) 2^26 + (w_b >> 6)) 2^-53 (exact). */
+static double o_u53(uint32_t wa, uint32_t wb)
+{
+    return ((double)(wa >> 5) * 67108864.0 + (double)(wb >> 6)) * 0x1p-53;
+}
+
+/* Candidate k of the RSA stream: centre u_a * L_a per axis, axes 0 and 1 from
+ * the words of call 0 and axis 2 from the first two words of call 1 (counter
+ * (k_lo, k_hi, call, 2)); a product that rounds up to L_a is folded to 0.
+ * Platelets: unit normal from the sphere-point method of Alg. 3's random
+ * vector with length 1, counter (k_lo, k_hi, call, 3). */
+void o_rsa_candidate(int dim, int shape, const double box[3], uint64_t seed, uint64_t k,
+                     double x[3], double nrm[3])
+{
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {(uint32_t)k, (uint32_t)(k >> 32), 0u, 2u}, W[4];
+    o_philox4x32(ctr, key, W);
+    x[0] = o_u53(W[0], W[1]) * box[0];
+    x[1] = o_u53(W[2], W[3]) * box[1];
+    x[2] = 0.0;
+    if (dim == 3) {
+        ctr[2] = 1u;
+        o_philox4x32(ctr, key, W);
+        x[2] = o_u53(W[0], W[1]) * box[2];
+    }
+    for (int a = 0; a < dim; ++a)
+        if (x[a] >= box[a]) x[a] = 0.0;
+    if (shape == O_PLATELET)
+        o_unitvec(3, seed, (uint32_t)k, (uint32_t)(k >> 32), 0, 0, 0, 3, 1.0, nrm);
+}
+
+/* Classical RSA of n equal particles (balls of radius `radius`, or platelets
+ * of radius `radius`): candidates are drawn in stream order and kept when
+ * they meet no particle kept earlier (balls: q <= (R + R)^2 with the
+ * minimum image of candidate - kept; platelets: the disk test with the kept
+ * particle as disk 1).  Kept candidates are numbered 0, 1, ... in the order
+ * kept; pos/nrm are [3n] rows (z = 0 in 2D), src[i] (nullable) is the
+ * candidate index of particle i.  *drawn = candidates drawn (the index of
+ * the last kept one plus 1), *placed = particles placed.  Returns O_ENOTCONV
+ * when max_candidates are drawn before n are placed. */
+int o_rsa(int dim, int shape, int64_t n, const double box[3], double radius, uint64_t seed,
+          int64_t max_candidates, double *pos, double *nrm, int64_t *src, int64_t *drawn,
+          int64_t *placed)
+{
+    if ((dim != 2 && dim != 3) || (shape != O_BALL && shape != O_PLATELET) ||
+        (shape == O_PLATELET && dim != 3) || n < 0 || !(radius >= 0.0) || isinf(radius))
+        return O_EINVAL;
+    for (int a = 0; a < dim; ++a)
+        if (!(box[a] > 0.0) || isinf(box[a])) return O_EINVAL;
+    const double sig = radius + radius;
+    int64_t kept = 0, k = 0;
+    while (kept < n) {
+        if (k >= max_candidates) {
+            *drawn = k;
+            *placed = kept;
+            return O_ENOTCONV;
+        }
+        double x[3], m[3] = {0.0, 0.0, 0.0};
+        o_rsa_candidate(dim, shape, box, seed, (uint64_t)k, x, m);
+        int hit = 0;
+        for (int64_t j = 0; j < kept && !hit; ++j) {
+            const double *y = &pos[3 * j];
+            if (shape == O_BALL) {
+                double d0 = o_minimg(x[0] - y[0], box[0]);
+                double d1 = o_minimg(x[1] - y[1], box[1]);
+                double q = d0 * d0 + d1 * d1;
+                if (dim == 3) {
+                    double d2 = o_minimg(x[2] - y[2], box[2]);
+                    q = q + d2 * d2;
+                }
+                hit = q <= sig * sig;
+            } else {
+                hit = o_disks_intersect(y, &nrm[3 * j], radius, x, m, radius, box);
+            }
+        }
+        if (!hit) {
+            for (int a = 0; a < 3; ++a) {
+                pos[3 * kept + a] = x[a];
+                if (nrm) nrm[3 * kept + a] = m[a];
+            }
+            if (src) src[kept] = k;
+            kept++;
+        }
+        k++;
+    }
+    *drawn = k;
+    *placed = kept;
     return O_OK;
 }
 

@@ -1,0 +1,209 @@
+"""Pins of the oracle's random sequential addition (the non-overlapping
+start of Sec. 2 at f0), independent of its own loop: the candidate stream
+from rocRAND's Philox words, the sequential-greedy characterisation checked
+with a k-d tree (and, for platelets, an independent disk formulation), and
+the low-coverage statistics of RSA (available area 1 - 4t + (6 sqrt3/pi) t^2
+for disks, 1 - 8t + 17 t^2 for spheres, Onsager's excluded volume pi^2 a^3
+for thin disks)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import rocrand_ref
+from tests.test_oracle_geometry import _chords_overlap_ref
+
+BALL, PLATELET = 0, 1
+
+
+def _radius_for(dim, n, f0, box):
+    vol = float(np.prod(box[:dim]))
+    if dim == 2:
+        return math.sqrt(f0 * vol / (math.pi * n))
+    return (f0 * vol / (4.0 / 3.0 * math.pi * n)) ** (1.0 / 3.0)
+
+
+def test_candidate_stream_from_rocrand_words():
+    """Centre of candidate k: 53-bit uniforms built in exact integer
+    arithmetic from rocRAND's words at counters (k_lo, k_hi, call, 2)."""
+    seed = 0x1234_5678_9ABC_DEF1
+    box = (1.0, 0.7, 1.3)
+    ks = np.array([0, 1, 2, 77, 2**31 + 3, 2**32 + 5, 2**40 + 17], dtype=np.int64)
+    x, m = oracle.rsa_candidates(3, BALL, box, seed, ks)
+    assert not m.any()
+    key = np.array([[seed & 0xFFFFFFFF, seed >> 32]] * len(ks), dtype=np.uint32)
+    for call in (0, 1):
+        ctr = np.zeros((len(ks), 4), dtype=np.uint32)
+        ctr[:, 0] = ks & 0xFFFFFFFF
+        ctr[:, 1] = ks >> 32
+        ctr[:, 2] = call
+        ctr[:, 3] = 2
+        W = rocrand_ref.philox4x32(ctr, key).astype(np.int64)
+        pairs = [(0, 1), (2, 3)] if call == 0 else [(0, 1)]
+        for a, (i, j) in enumerate(pairs):
+            axis = a if call == 0 else 2
+            for r in range(len(ks)):
+                num = (int(W[r, i]) >> 5) * 2**26 + (int(W[r, j]) >> 6)
+                u = num / 2**53  # exact: a 53-bit integer over a power of two
+                want = u * box[axis]
+                if want >= box[axis]:
+                    want = 0.0
+                assert x[r, axis] == want, (r, axis)
+    # 2D uses the first call only, with the same words
+    x2, _ = oracle.rsa_candidates(2, BALL, box[:2], seed, ks)
+    assert np.array_equal(x2[:, :2], x[:, :2]) and not x2[:, 2].any()
+
+
+def test_platelet_candidate_normals_are_unit_sphere_points():
+    ks = np.arange(2000)
+    _, m = oracle.rsa_candidates(3, PLATELET, (1.0, 1.0, 1.0), 9, ks)
+    assert np.allclose(np.linalg.norm(m, axis=1), 1.0, atol=4e-16)
+    # isotropy: mean ~ 0, second moments ~ I/3 (5 sigma)
+    assert np.all(np.abs(m.mean(axis=0)) < 5 * math.sqrt(1 / 3 / len(ks)))
+    cov = m.T @ m / len(ks)
+    assert np.allclose(cov, np.eye(3) / 3, atol=5 * math.sqrt(4 / 45 / len(ks)))
+    # the same words as Alg. 3's random vector of length 1 at that counter
+    v, _ = oracle.unitvec(3, 9, 123, 0, 0, 0, 0, 3, 1.0)
+    assert np.array_equal(m[123], v)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_zero_radius_keeps_the_first_candidates(dim):
+    rc, pos, _, src, drawn, placed = oracle.rsa(dim, BALL, 500, (1.0,) * dim, 0.0, 4)
+    assert rc == 0 and drawn == 500 and placed == 500
+    assert np.array_equal(src, np.arange(500))
+    x, _ = oracle.rsa_candidates(dim, BALL, (1.0,) * dim, 4, np.arange(500))
+    assert np.array_equal(pos, x[:, :dim].T)
+
+
+def test_empty_single_and_invalid():
+    rc, pos, _, src, drawn, placed = oracle.rsa(3, BALL, 0, (1.0, 1.0, 1.0), 0.1, 1)
+    assert rc == 0 and drawn == 0 and placed == 0 and pos.shape == (3, 0)
+    rc, pos, _, src, drawn, placed = oracle.rsa(3, BALL, 1, (1.0, 1.0, 1.0), 0.4, 1)
+    assert rc == 0 and drawn == 1 and list(src) == [0]
+    for args in [(4, BALL, 5, (1.0,) * 3, 0.1), (2, PLATELET, 5, (1.0, 1.0), 0.1),
+                 (3, BALL, 5, (1.0,) * 3, -0.1), (3, BALL, 5, (1.0, 0.0, 1.0), 0.1),
+                 (3, BALL, 5, (1.0,) * 3, float("nan"))]:
+        with pytest.raises(RuntimeError):
+            oracle.rsa(*args, seed=1)
+
+
+def test_jammed_box_reports_not_converged():
+    """Disks of radius 0.3 in the unit square: at most a handful fit, so
+    ten are never placed and the candidate budget runs out."""
+    rc, pos, _, src, drawn, placed = oracle.rsa(2, BALL, 10, (1.0, 1.0), 0.3, 3,
+                                                max_candidates=5000)
+    assert rc == oracle.ENOTCONV and drawn == 5000 and 1 <= placed < 10
+
+
+def _check_greedy_balls(dim, box, radius, seed, pos, src, drawn):
+    """The sequential rule, checked from the outside: kept particles are the
+    stream's candidates at increasing indices, no two kept ones touch, and
+    every skipped candidate touches one kept before it."""
+    from scipy.spatial import cKDTree
+    n = pos.shape[1]
+    assert np.all(np.diff(src) > 0) and (n == 0 or src[-1] == drawn - 1)
+    cand, _ = oracle.rsa_candidates(dim, BALL, box, seed, np.arange(drawn))
+    cand = cand[:, :dim]
+    assert np.array_equal(pos.T, cand[src])
+    sig = 2.0 * radius
+    tree = cKDTree(pos.T, boxsize=np.asarray(box[:dim]))
+    assert len(tree.query_pairs(sig * (1 - 1e-9))) == 0
+    kept = np.zeros(drawn, dtype=bool)
+    kept[src] = True
+    rejected = np.nonzero(~kept)[0]
+    hits = tree.query_ball_point(cand[rejected], sig * (1 + 1e-9))
+    for k, h in zip(rejected, hits):
+        assert len(h) and src[min(h)] < k, k
+    return len(rejected)
+
+
+@pytest.mark.parametrize("dim,n,f0,box", [(2, 3000, 0.3, (1.0, 1.0)), (3, 3000, 0.1, (1.0, 1.0, 1.0)),
+                                          (3, 2500, 0.25, (0.7, 1.0, 1.6)),
+                                          (2, 2000, 0.45, (1.0, 0.4))])
+def test_greedy_characterisation_balls(dim, n, f0, box):
+    radius = _radius_for(dim, n, f0, box)
+    rc, pos, _, src, drawn, placed = oracle.rsa(dim, BALL, n, box, radius, 40 + dim)
+    assert rc == 0 and placed == n
+    rej = _check_greedy_balls(dim, box, radius, 40 + dim, pos, src, drawn)
+    assert rej > 0
+
+
+def _minimg(d, box):
+    return d - np.asarray(box) * np.round(d / np.asarray(box))
+
+
+def test_greedy_characterisation_platelets():
+    from scipy.spatial import cKDTree
+    box = (1.0, 1.0, 1.0)
+    a, n, seed = 0.06, 600, 12
+    rc, pos, nrm, src, drawn, placed = oracle.rsa(3, PLATELET, n, box, a, seed)
+    assert rc == 0 and placed == n
+    cand, cn = oracle.rsa_candidates(3, PLATELET, box, seed, np.arange(drawn))
+    assert np.array_equal(pos.T, cand[src]) and np.array_equal(nrm, cn[src])
+    tree = cKDTree(cand, boxsize=np.asarray(box))
+    kept = np.zeros(drawn, dtype=bool)
+    kept[src] = True
+    checked = 0
+    for k in range(drawn):
+        # candidates within 2a that were kept before k
+        near = [j for j in tree.query_ball_point(cand[k], 2 * a * (1 + 1e-9)) if j < k and kept[j]]
+        meets = False
+        for j in near:
+            c2 = cand[j] + _minimg(cand[k] - cand[j], box)
+            hit, margin = _chords_overlap_ref(cand[j], cn[j], a, c2, cn[k], a)
+            if margin < 1e-9:
+                continue
+            checked += 1
+            meets = meets or hit
+        assert meets != kept[k], k
+    assert checked > 100
+
+
+def _phi_sum(n, step, coeffs):
+    """Sum over placements i of (1/Phi(t_i) - 1) and its variance, Phi a
+    polynomial in the covered fraction t_i = i * step."""
+    t = np.arange(n) * step
+    phi = np.ones_like(t)
+    for p, c in enumerate(coeffs, start=1):
+        phi = phi + c * t**p
+    return float(np.sum(1 / phi - 1)), float(np.sum((1 - phi) / phi**2))
+
+
+@pytest.mark.parametrize("dim,t_final,coeffs", [(2, 0.1, (-4.0, 6 * math.sqrt(3) / math.pi)),
+                                                (3, 0.03, (-8.0, 17.0))])
+def test_low_coverage_statistics_balls(dim, t_final, coeffs):
+    """Extra candidates needed to place n particles: the mean over 8 seeds
+    lies within 4 sigma of the sum of 1/Phi - 1 with the second-order
+    available-area expansion (the first-order term alone is off by ~2.5
+    sigma per seed, and a wrong contact distance by far more)."""
+    n = 4000
+    box = (1.0,) * dim
+    radius = _radius_for(dim, n, t_final, box)
+    extra = []
+    for seed in range(8):
+        rc, _, _, _, drawn, _ = oracle.rsa(dim, BALL, n, box, radius, 500 + seed)
+        assert rc == 0
+        extra.append(drawn - n)
+    mean, var = _phi_sum(n, t_final / n, coeffs)
+    sd = math.sqrt(var / 8)
+    assert abs(np.mean(extra) - mean) < 4 * sd, (np.mean(extra), mean, sd)
+    lin, _ = _phi_sum(n, t_final / n, coeffs[:1])
+    assert abs(lin - mean) > 2 * sd  # the test resolves the second-order term
+
+
+def test_low_density_statistics_platelets():
+    """Thin disks with isotropic normals exclude pi^2 a^3 (Onsager) at low
+    density: mean extra candidates over 8 seeds against the first-order sum,
+    within 4 sigma plus 10% for the unknown second-order term."""
+    n, a = 3000, 0.02
+    step = math.pi**2 * a**3
+    extra = []
+    for seed in range(8):
+        rc, _, _, _, drawn, _ = oracle.rsa(3, PLATELET, n, (1.0, 1.0, 1.0), a, 700 + seed)
+        assert rc == 0
+        extra.append(drawn - n)
+    mean, var = _phi_sum(n, step, (-1.0,))
+    sd = math.sqrt(var / 8)
+    assert abs(np.mean(extra) - mean) < 4 * sd + 0.1 * mean, (np.mean(extra), mean, sd)
