@@ -203,6 +203,48 @@ srm_status srm_percolation(srm_ctx *ctx, double gap, int32_t *wraps);
  * Errors: SRM_EINVAL. */
 srm_status srm_critical_gap(srm_ctx *ctx, double lo, double hi, int32_t iters, double *gap_c);
 
+/* ---- initial configuration: random sequential addition --------------- */
+
+/* Result counters of srm_rsa. */
+typedef struct {
+    int64_t drawn;    /* candidates drawn: index of the last one kept + 1, or max_candidates */
+    int64_t placed;   /* particles placed (n unless SRM_ENOTCONV) */
+    int32_t batches;  /* candidate batches run */
+    int32_t rounds;   /* ordering rounds, summed over the batches */
+} srm_rsa_info;
+
+/* Classical random sequential addition of n equal particles, the
+ * non-overlapping start at a low volume fraction f0 that Sec. 2 and
+ * Algorithm 1 begin the swelling from ("RSA procedure").  Candidates
+ * k = 0, 1, 2, ... are drawn from Philox4x32-10 keyed by `seed`: the centre
+ * from counters (k_lo, k_hi, call, 2) -- per axis a 53-bit uniform
+ * ((w_a >> 5) * 2^26 + (w_b >> 6)) * 2^-53 times L_a, words (0,1) and (2,3)
+ * of call 0 for x and y, words (0,1) of call 1 for z, a product equal to L_a
+ * folded to 0 -- and, for platelets (3D), a unit normal from Algorithm 3's
+ * random vector of length 1 with counter (k_lo, k_hi, attempt, 3).  A
+ * candidate is kept when it meets no particle kept before it (balls of
+ * radius `radius`: minimum-image q <= (radius + radius)^2, touching counts;
+ * platelets of radius `radius`: the thin-disk test with the earlier one as
+ * disk 1) and gets the next particle id.  The result is that sequence
+ * exactly, whatever `batch` (candidates per GPU batch, 0 = automatic, at
+ * most 2^28).
+ *   pos      dim * n doubles (SoA, id order), written;
+ *   normals  3 * n doubles (platelets; NULL for balls), written;
+ *   src      n int64 candidate indices (nullable), written;
+ *   mem_kind SRM_MEM_HOST or SRM_MEM_DEVICE for these three buffers;
+ *   hip_stream the stream all work runs on (NULL = null stream); the call
+ *            synchronises it before returning;
+ *   info     nullable.
+ * Device memory is allocated for the call and freed before it returns.
+ * Pass pos/normals with s0 = radius (monodisperse, rho = 1) to srm_init.
+ * Errors: SRM_EINVAL (nothing written); SRM_ENOMEM; SRM_ENOTCONV when
+ * max_candidates are drawn before n are placed (the first info->placed
+ * particles are written). */
+srm_status srm_rsa(int32_t dim, int32_t shape, int64_t n, const double *box, double radius,
+                   uint64_t seed, int64_t max_candidates, int64_t batch, double *pos,
+                   double *normals, int64_t *src, int32_t mem_kind, void *hip_stream,
+                   srm_rsa_info *info);
+
 /* ---- differentiable descriptor: soft g(r) + overlap energy -------------- */
 
 /* A workspace for configurations of n particles in a fixed periodic box.

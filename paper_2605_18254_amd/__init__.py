@@ -15,7 +15,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["SRM", "SrmError", "lib", "LIB_PATH", "BALL", "PLATELET", "MAIN", "SHAKE"]
+__all__ = ["SRM", "SrmError", "rsa", "lib", "LIB_PATH", "BALL", "PLATELET", "MAIN", "SHAKE"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libsrm.so")
 
@@ -25,7 +25,7 @@ MAIN, SHAKE = 0, 1
 OK, EINVAL, ENOMEM, EDEVICE, EOVERLAP, ENOTCONV, ECAPACITY = 0, -1, -2, -3, -4, -5, -6
 
 SYMBOLS = ["srm_init", "srm_sweep", "srm_run_to_fraction", "srm_pairs", "srm_rdf", "srm_nearest",
-           "srm_percolation", "srm_critical_gap",
+           "srm_percolation", "srm_critical_gap", "srm_rsa",
            "srm_get_state", "srm_free", "srm_last_error", "srm_grid", "srm_cells", "srm_pass",
            "srm_last_acc", "srm_set_state", "srm_softrdf_create", "srm_softrdf_forward",
            "srm_softrdf_backward", "srm_softrdf_free", "srm_profile_enable", "srm_profile_read",
@@ -58,6 +58,11 @@ class Profile(C.Structure):
                 ("bins", C.c_int64), ("launches_migrate", C.c_int64), ("passes", C.c_int64),
                 ("checks", C.c_int64), ("ms_migrate_main", C.c_double),
                 ("main_kernels", C.c_int64), ("trials", C.c_int64)]
+
+
+class RsaInfo(C.Structure):
+    _fields_ = [("drawn", C.c_int64), ("placed", C.c_int64), ("batches", C.c_int32),
+                ("rounds", C.c_int32)]
 
 
 class RunInfo(C.Structure):
@@ -95,6 +100,8 @@ def lib():
     L.srm_percolation.argtypes = [vp, C.c_double, C.POINTER(C.c_int32)]
     L.srm_critical_gap.argtypes = [vp, C.c_double, C.c_double, C.c_int32, dp]
     L.srm_get_state.argtypes = [vp, vp, vp, dp, C.POINTER(C.c_int64), C.c_int32]
+    L.srm_rsa.argtypes = [C.c_int32, C.c_int32, C.c_int64, dp, C.c_double, C.c_uint64, C.c_int64,
+                          C.c_int64, vp, vp, vp, C.c_int32, vp, C.POINTER(RsaInfo)]
     L.srm_free.argtypes = [vp]
     L.srm_last_error.argtypes = []
     L.srm_last_error.restype = C.c_char_p
@@ -166,6 +173,41 @@ def debug_unitvec(dim, seed, t, kind, k, l, stream, length, n) -> np.ndarray:
     _check(lib().srm_debug_unitvec(int(dim), int(seed), int(t), word, int(stream), float(length),
                                    int(n), out.ctypes.data_as(C.POINTER(C.c_double))))
     return out
+
+
+def rsa(dim, shape, n, box, radius, seed, max_candidates=None, batch=0, device=False):
+    """Random sequential addition of n equal particles on the GPU (srm_rsa).
+
+    Returns a dict: status (OK or ENOTCONV), pos (dim, n), normals (3, n) or
+    None, src (n,) candidate indices, drawn, placed, batches, rounds.  With
+    device=True the arrays are torch CUDA tensors written on torch's current
+    stream; otherwise numpy arrays.  Other errors raise SrmError."""
+    dim, shape, n = int(dim), int(shape), int(n)
+    box3 = (C.c_double * 3)(*(list(box) + [1.0] * (3 - len(box))))
+    if max_candidates is None:
+        max_candidates = 1000 * max(n, 1)
+    stream = None
+    if device:
+        import torch
+        pos = torch.zeros((dim, n), dtype=torch.float64, device="cuda")
+        nrm = torch.zeros((3, n), dtype=torch.float64, device="cuda") if shape == PLATELET else None
+        src = torch.zeros(n, dtype=torch.int64, device="cuda")
+        stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        ptr = lambda a: None if a is None else C.c_void_p(a.data_ptr())  # noqa: E731
+        kind = MEM_DEVICE
+    else:
+        pos = np.zeros((dim, n))
+        nrm = np.zeros((3, n)) if shape == PLATELET else None
+        src = np.zeros(n, dtype=np.int64)
+        ptr = lambda a: None if a is None else C.c_void_p(a.ctypes.data)  # noqa: E731
+        kind = MEM_HOST
+    info = RsaInfo()
+    st = lib().srm_rsa(dim, shape, n, box3, float(radius), int(seed), int(max_candidates),
+                       int(batch), ptr(pos), ptr(nrm), ptr(src), kind, stream, C.byref(info))
+    if st not in (OK, ENOTCONV):
+        _check(st)
+    return dict(status=st, pos=pos, normals=nrm, src=src, drawn=info.drawn, placed=info.placed,
+                batches=info.batches, rounds=info.rounds)
 
 
 class SRM:

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libsrm.so")
-SOURCES = ["srm_api.hip", "k_bin.hip", "k_migrate.hip", "k_pairs.hip", "k_softrdf.hip", "srm_batch.hip", "k_diag.hip", "k_perc.hip"]
+SOURCES = ["srm_api.hip", "k_bin.hip", "k_migrate.hip", "k_pairs.hip", "k_softrdf.hip", "srm_batch.hip", "k_diag.hip", "k_perc.hip", "srm_rsa.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

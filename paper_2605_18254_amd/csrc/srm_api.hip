@@ -43,6 +43,10 @@ srm_status fail(srm_status st, const char *fmt, ...)
 
 }  // namespace
 
+namespace srm {
+void set_last_error(const char *msg) { g_last_error = msg; }
+}  // namespace srm
+
 struct srm_ctx {
     srm_params p{};
     int device = 0;

@@ -45,6 +45,9 @@ struct ColourLattice {
     int32_t count;  // colour cells in this phase
 };
 
+// Sets the message srm_last_error() returns (thread-local).
+void set_last_error(const char *msg);
+
 // Host launchers (all enqueue on `stream`).
 hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t stream);
 hipError_t launch_fill_u8(uint8_t *a, int64_t n, uint8_t v, hipStream_t stream);

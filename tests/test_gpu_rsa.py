@@ -1,0 +1,176 @@
+"""GPU random sequential addition (srm_rsa) against the oracle's sequential
+RSA: kept particles, their normals, candidate indices and the number of
+candidates drawn are identical for every batch size; at full size the
+sequential rule is checked from the outside with a k-d tree; an SRM run
+from an RSA start (the Sec. 3.1 protocol) equals the oracle sweep by sweep.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import srm_inputs
+
+pytestmark = pytest.mark.gpu
+
+BALL, PLATELET = 0, 1
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def srm():
+    import paper_2605_18254_amd as m
+    m.lib()
+    return m
+
+
+def _radius(dim, n, f0, box):
+    return srm_inputs.target_scale(dim, BALL, f0, tuple(box) + (1.0,) * (3 - len(box)), None, n)
+
+
+def _same(g, o, shape):
+    rc, pos, nrm, src, drawn, placed = o
+    assert g["status"] == rc and g["placed"] == placed and g["drawn"] == drawn
+    assert np.array_equal(g["pos"][:, :placed], pos[:, :placed])
+    assert np.array_equal(g["src"][:placed], src[:placed])
+    if shape == PLATELET:
+        assert np.array_equal(g["normals"][:, :placed], nrm[:placed].T)
+
+
+@pytest.mark.parametrize("dim,n,f0,box", [(2, 3000, 0.3, (1.0, 1.0)), (3, 5000, 0.1, (1.0, 1.0, 1.0)),
+                                          (3, 4000, 0.3, (0.7, 1.0, 1.6)),
+                                          (2, 2500, 0.5, (1.0, 0.45))])
+def test_balls_match_oracle_for_every_batch_size(srm, dim, n, f0, box):
+    radius = _radius(dim, n, f0, box)
+    seed = 17 + dim
+    ref = oracle.rsa(dim, BALL, n, box, radius, seed)
+    assert ref[0] == 0
+    for batch in (0, 257, 1000, 100000):
+        g = srm.rsa(dim, BALL, n, box, radius, seed, batch=batch)
+        _same(g, ref, BALL)
+        _say(f"rsa {dim}D n={n} f0={f0} batch={batch}: drawn {g['drawn']}, "
+             f"{g['batches']} batches, {g['rounds']} rounds")
+
+
+@pytest.mark.parametrize("n,a,batch", [(600, 0.06, 0), (600, 0.06, 333), (2000, 0.05, 0)])
+def test_platelets_match_oracle(srm, n, a, batch):
+    ref = oracle.rsa(3, PLATELET, n, (1.0, 1.0, 1.0), a, 12)
+    assert ref[0] == 0
+    g = srm.rsa(3, PLATELET, n, (1.0, 1.0, 1.0), a, 12, batch=batch)
+    _same(g, ref, PLATELET)
+    _say(f"rsa platelets n={n} a={a}: drawn {g['drawn']}, {g['rounds']} rounds")
+
+
+def test_edge_cases(srm):
+    # zero radius: the first n candidates
+    g = srm.rsa(3, BALL, 700, (1.0, 1.0, 1.0), 0.0, 4)
+    assert g["drawn"] == 700 and np.array_equal(g["src"], np.arange(700))
+    x, _ = oracle.rsa_candidates(3, BALL, (1.0, 1.0, 1.0), 4, np.arange(700))
+    assert np.array_equal(g["pos"], x.T)
+    # empty and single
+    g = srm.rsa(2, BALL, 0, (1.0, 1.0), 0.1, 1)
+    assert g["status"] == 0 and g["drawn"] == 0 and g["pos"].shape == (2, 0)
+    g = srm.rsa(3, BALL, 1, (1.0, 1.0, 1.0), 0.4, 1)
+    assert g["drawn"] == 1 and list(g["src"]) == [0]
+    # jammed: the budget runs out, the placed prefix equals the oracle's
+    ref = oracle.rsa(2, BALL, 10, (1.0, 1.0), 0.3, 3, max_candidates=5000)
+    for batch in (0, 64):
+        g = srm.rsa(2, BALL, 10, (1.0, 1.0), 0.3, 3, max_candidates=5000, batch=batch)
+        assert g["status"] == srm.ENOTCONV
+        _same(g, ref, BALL)
+    g = srm.rsa(3, BALL, 5, (1.0, 1.0, 1.0), 0.01, 3, max_candidates=0)
+    assert g["status"] == srm.ENOTCONV and g["placed"] == 0 and g["drawn"] == 0
+    # a candidate budget that ends inside a batch
+    ref = oracle.rsa(3, BALL, 3000, (1.0, 1.0, 1.0), _radius(3, 3000, 0.3, (1, 1, 1)), 8,
+                     max_candidates=3100)
+    g = srm.rsa(3, BALL, 3000, (1.0, 1.0, 1.0), _radius(3, 3000, 0.3, (1, 1, 1)), 8,
+                max_candidates=3100, batch=1024)
+    assert ref[0] == srm.ENOTCONV
+    _same(g, ref, BALL)
+
+
+def test_invalid_arguments(srm):
+    bad = [dict(dim=4, shape=BALL, box=(1, 1, 1), radius=0.1),
+           dict(dim=2, shape=PLATELET, box=(1, 1), radius=0.1),
+           dict(dim=3, shape=BALL, box=(1, 0, 1), radius=0.1),
+           dict(dim=3, shape=BALL, box=(1, 1, 1), radius=-1.0),
+           dict(dim=3, shape=BALL, box=(1, 1, 1), radius=float("inf"))]
+    for kw in bad:
+        with pytest.raises(srm.SrmError) as e:
+            srm.rsa(kw["dim"], kw["shape"], 10, kw["box"], kw["radius"], 1)
+        assert e.value.status == srm.EINVAL
+    with pytest.raises(srm.SrmError):
+        srm.rsa(3, BALL, 10, (1, 1, 1), 0.1, 1, batch=-5)
+
+
+def test_device_buffers_equal_host(srm):
+    import torch
+    r = _radius(3, 20000, 0.1, (1, 1, 1))
+    h = srm.rsa(3, BALL, 20000, (1, 1, 1), r, 5)
+    d = srm.rsa(3, BALL, 20000, (1, 1, 1), r, 5, device=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(d["pos"].cpu().numpy(), h["pos"])
+    assert np.array_equal(d["src"].cpu().numpy(), h["src"])
+    hp = srm.rsa(3, PLATELET, 500, (1, 1, 1), 0.06, 5)
+    dp = srm.rsa(3, PLATELET, 500, (1, 1, 1), 0.06, 5, device=True)
+    assert np.array_equal(dp["normals"].cpu().numpy(), hp["normals"])
+
+
+@pytest.mark.parametrize("dim,n,f0", [(3, 4_000_000, 0.1), (2, 2_000_000, 0.1)])
+def test_full_size_sequential_rule(srm, dim, n, f0):
+    """Millions of particles at f0 = 0.1: kept particles are the stream's
+    candidates at increasing indices (sampled against the oracle's stream),
+    no two of them meet, and sampled skipped candidates each meet a particle
+    kept before them (k-d tree, independent of both sides)."""
+    from scipy.spatial import cKDTree
+    box = (1.0,) * dim
+    radius = _radius(dim, n, f0, box)
+    g = srm.rsa(dim, BALL, n, box, radius, 99)
+    assert g["status"] == 0 and g["placed"] == n
+    pos, src, drawn = g["pos"], g["src"], g["drawn"]
+    _say(f"rsa {dim}D n={n}: drawn {drawn}, {g['batches']} batches, {g['rounds']} rounds")
+    assert np.all(np.diff(src) > 0) and src[-1] == drawn - 1
+    rng = np.random.default_rng(3)
+    ids = rng.choice(n, 2000, replace=False)
+    cand, _ = oracle.rsa_candidates(dim, BALL, box, 99, src[ids])
+    assert np.array_equal(pos[:, ids], cand[:, :dim].T)
+    tree = cKDTree(pos.T, boxsize=np.asarray(box))
+    sig = 2.0 * radius
+    assert len(tree.query_pairs(sig * (1 - 1e-9))) == 0
+    kept = np.zeros(drawn, dtype=bool)
+    kept[src] = True
+    skipped = np.nonzero(~kept)[0]
+    ks = rng.choice(skipped, min(3000, len(skipped)), replace=False)
+    cx, _ = oracle.rsa_candidates(dim, BALL, box, 99, ks)
+    hits = tree.query_ball_point(cx[:, :dim], sig * (1 + 1e-9))
+    for k, h in zip(ks, hits):
+        assert len(h) and src[min(h)] < k, k
+
+
+def test_srm_from_rsa_start_matches_oracle(srm):
+    """The Sec. 3.1 protocol at small size: RSA at f0 = 0.1, then SRM to
+    f = 0.4 (3D) with every sweep equal to the oracle's."""
+    n = 5000
+    w = srm_inputs.make("spheres3d", n=n, seed=31, f_target=0.4, c_w=0.02)
+    r0 = _radius(3, n, 0.1, (1.0, 1.0, 1.0))
+    start = srm.rsa(3, BALL, n, (1.0, 1.0, 1.0), r0, 31)
+    ref = oracle.rsa(3, BALL, n, (1.0, 1.0, 1.0), r0, 31)
+    assert np.array_equal(start["pos"], ref[1])
+    o = oracle.Oracle.from_workload(w, pos=ref[1], s0=r0)
+    g = srm.SRM.from_workload(w, pos=start["pos"], s0=r0)
+    sweeps = 0
+    while o.s < w.s_target and sweeps < 300:
+        io, acc_o = o.sweep()
+        ig = g.sweep()
+        sweeps += 1
+        assert ig["committed"] == io["committed"] and ig["s"] == o.s, sweeps
+    pos, _, s, t = g.state()
+    assert np.array_equal(pos, o.soa()) and s == o.s == w.s_target
+    _say(f"RSA f0=0.1 -> SRM f=0.4: {sweeps} sweeps")
+    g.close()
