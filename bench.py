@@ -91,6 +91,8 @@ def parse():
                     help="fraction of the cell layers the oracle sample covers")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-ensemble and gradient measurements")
+    ap.add_argument("--extras", default="n_scaling,platelets,platelet_protocol,batched,gradient",
+                    help="comma-separated extras to run")
     ap.add_argument("--batch-sweeps", type=int, default=400,
                     help="sweep budget of every RVE of the batched ensemble")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -232,12 +234,12 @@ def platelet_extra(max_sweeps):
                        "c_m=0.1*s_target, c_n=c_m/a_t, N_k=N_l=8")
     return out
 
-def n_scaling_extra():
-    """Wall time to reach the target from the uniform start (s = 0) for N =
-    1e3 .. 1e7 spheres in the unit cube at f = 0.35 (the benchmark's
-    parameters), and the fitted exponent of time in N (the paper reports
-    the growth of its run time with N; the sweep count is nearly independent
-    of N)."""
+def n_scaling_extra(sizes=(1_000, 10_000, 100_000, 1_000_000, 10_000_000)):
+    """The paper's efficiency protocol (Sec. 3.1, Fig. 2): an RSA start at
+    f0 = 0.1 (srm_rsa), then SRM to f = 0.4 in 3D and 0.5 in 2D with a large
+    swelling step (c_w = 0.02, c_m = 0.1 s_t), for N = 1e3 .. 1e7 in the unit
+    box; wall times of both stages, and the fitted exponent of the total time
+    in N for N >= 1e5 (the paper's optimised CPU code grows as N^1.15)."""
     import math
 
     import torch
@@ -245,29 +247,48 @@ def n_scaling_extra():
     import paper_2605_18254_amd as srm
     import srm_inputs
 
-    rows = []
-    warm = srm.SRM.from_workload(srm_inputs.make("spheres3d", n=1_000), device=True)
-    warm.run(1000)  # first launches load the kernels; keep them out of the timings
-    warm.close()
-    for n in (1_000, 10_000, 100_000, 1_000_000, 10_000_000):
-        w = srm_inputs.make("spheres3d", n=n)
-        g = srm.SRM.from_workload(w, device=True)
+    def one(dim, n, f_t):
+        name = "spheres3d" if dim == 3 else "disks2d"
+        w = srm_inputs.make(name, n=n, seed=1, f_target=f_t, c_w=0.02)
+        r0 = srm_inputs.target_scale(dim, srm.BALL, 0.1, w.box, None, n)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st, info = g.run(1000)
+        start = srm.rsa(dim, srm.BALL, n, w.box[:dim], r0, 1, device=True)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        g = srm.SRM.from_workload(w, pos=start["pos"], s0=r0)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st, info = g.run(2000)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
         g.close()
-        rows.append({"n": n, "converged": st == 0, "sweeps": info["sweeps"],
-                     "passes": info["passes"], "s": dt, "updates_per_s": info["updates"] / dt})
-        _say(f"n-scaling: {rows[-1]}")
-    big = [r for r in rows if r["n"] >= 100_000]
-    xs = [math.log(r["n"]) for r in big]
-    ys = [math.log(r["s"]) for r in big]
-    mx, my = sum(xs) / len(xs), sum(ys) / len(ys)
-    slope = sum((x - mx) * (y - my) for x, y in zip(xs, ys)) / sum((x - mx) ** 2 for x in xs)
-    return {"workload": "spheres3d, unit cube, f 0.35, seed 1, uniform start at s = 0",
-            "runs": rows, "time_exponent_n_ge_1e5": slope}
+        return {"n": n, "rsa_s": t1 - t0, "rsa_candidates": start["drawn"],
+                "rsa_batches": start["batches"], "rsa_rounds": start["rounds"],
+                "init_s": t2 - t1, "srm_s": t3 - t2, "total_s": t3 - t0,
+                "converged": st == 0, "sweeps": info["sweeps"], "passes": info["passes"],
+                "srm_updates_per_s": info["updates"] / (t3 - t2)}
+
+    def slope(rows):
+        big = [r for r in rows if r["n"] >= 100_000]
+        if len(big) < 2:
+            return None
+        xs = [math.log(r["n"]) for r in big]
+        ys = [math.log(r["total_s"]) for r in big]
+        mx, my = sum(xs) / len(xs), sum(ys) / len(ys)
+        return sum((x - mx) * (y - my) for x, y in zip(xs, ys)) / sum((x - mx) ** 2 for x in xs)
+
+    out = {"protocol": "RSA f0 0.1, then SRM (c_w 0.02, c_m 0.1 s_t) to f 0.4 (3D) / 0.5 (2D), "
+                       "unit box, seed 1"}
+    for dim, f_t in ((3, 0.4), (2, 0.5)):
+        one(dim, 1_000, f_t)  # first launches load the kernels
+        rows = []
+        for n in sizes:
+            rows.append(one(dim, n, f_t))
+            _say(f"n-scaling {dim}D: {rows[-1]}")
+        out[f"{dim}d"] = {"runs": rows, "time_exponent_n_ge_1e5": slope(rows)}
+    return out
+
 
 def platelet_protocol_extra(densities=(1.0, 2.0, 5.0), n=20_000, relax_sweeps=100):
     """The paper's platelet application (Sec. 3.3, Figs. 8-9): 20000 platelets
@@ -470,7 +491,7 @@ def main():
     # the colour phases' main kernel alone (the tiled kernel on this workload)
     avg_launch_s = prof["ms_migrate_main"] / 1e3 / launches
     main_name = {1: "k_migrate_tile<3,false>", 2: "k_migrate_wave<3,false>",
-                 4: "k_migrate_ball<3,false>"}.get(prof["main_kernels"], "mixed")
+                 16: "k_migrate_tile_wide<3,false>"}.get(prof["main_kernels"], "mixed")
     traffic = recorded_traffic(main_name)
     upd_per_launch = updates / launches
     bytes_per_launch = ALG_BYTES_PER_UPDATE * upd_per_launch
@@ -512,11 +533,16 @@ def main():
                       "frac": (phase_bytes + BIN_BYTES * w.n * passes) / dt / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_extras:
-        out["extras"] = {"n_scaling": n_scaling_extra(),
-                         "platelets": platelet_extra(3000),
-                         "platelet_protocol": platelet_protocol_extra(),
-                         "batched": batched_extra(args.batch_sweeps),
-                         "gradient": grad_extra(20, 10)}
+        runs = {"n_scaling": n_scaling_extra,
+                "platelets": lambda: platelet_extra(3000),
+                "platelet_protocol": platelet_protocol_extra,
+                "batched": lambda: batched_extra(args.batch_sweeps),
+                "gradient": lambda: grad_extra(20, 10)}
+        names = [x for x in args.extras.split(",") if x]
+        unknown = [x for x in names if x not in runs]
+        if unknown:
+            raise SystemExit(f"unknown extras: {unknown}")
+        out["extras"] = {x: runs[x]() for x in names}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_fraction)
     print(json.dumps(out), flush=True)

@@ -342,9 +342,10 @@ typedef struct {
 
 /* Main migration kernel of a colour phase (srm_profile.main_kernels). */
 #define SRM_KERNEL_TILE 1     /* LDS-tiled, four lanes per cell */
-#define SRM_KERNEL_WAVE 2     /* one wavefront per crowded cell */
-#define SRM_KERNEL_CELL 4     /* one thread per cell (small grids) */
-#define SRM_KERNEL_PLATELET 8 /* platelets, one thread per cell */
+#define SRM_KERNEL_WAVE 2     /* one wavefront per cell (crowded or small grids) */
+#define SRM_KERNEL_CELL 4     /* reserved: one thread per cell (not selected) */
+#define SRM_KERNEL_PLATELET 8 /* platelets (with SRM_KERNEL_WAVE) */
+#define SRM_KERNEL_TILE_WIDE 16 /* LDS-tiled with a larger region (denser 3D grids) */
 
 /* Profiling switches, reset with the accumulated profile: bit 0 times the
  * phases above with hipEvents; bit 1 also counts trial moves (a small

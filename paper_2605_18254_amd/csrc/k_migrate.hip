@@ -16,6 +16,8 @@
 // see a periodic image: neither the trial position nor any candidate has
 // wrapped, and all differences are below L/2, so the minimum-image
 // correction is the identity there and is skipped.
+#include <math.h>
+
 #include "srm_cellpass.hpp"
 
 namespace srm {
@@ -24,20 +26,6 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// One thread per colour cell, candidates read from global memory (grids
-// too small for the tiled kernel).
-template <int DIM, bool POLY>
-__global__ void __launch_bounds__(kBlock) k_migrate_ball(PassArgs a, ColourLattice L)
-{
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= L.count) return;
-    const int32_t jx = t % L.h[0];
-    const int32_t r1 = t / L.h[0];
-    const int32_t jy = r1 % L.h[1];
-    const int32_t jz = r1 / L.h[1];
-    migrate_cell_global<DIM, POLY>(a, 2 * jx + L.off[0], 2 * jy + L.off[1],
-                                   (DIM == 3) ? 2 * jz + L.off[2] : 0);
-}
 
 // One 64-thread workgroup per colour cell (crowded cells).
 template <int DIM, bool POLY>
@@ -77,7 +65,7 @@ __global__ void __launch_bounds__(64) k_migrate_wave(PassArgs a, ColourLattice L
 // synchronisation in phase B.  A tile whose neighbourhood does not fit LDS
 // is queued for the global-memory kernel.
 
-template <int DIM, bool POLY>
+template <int DIM, bool POLY, bool WIDE = false>
 struct QuadCfg {
     static constexpr int T = (DIM == 3) ? 4 : 8;
     static constexpr int R = 2 * T + 1;
@@ -85,10 +73,13 @@ struct QuadCfg {
     static constexpr int kThreads = 256;
     static constexpr int kPer = (kCells + kThreads - 1) / kThreads;
     static constexpr int kNear = 11;    // near-list entries per particle
-    static constexpr int kOwn = 160;    // particles of the tile's own cells
+    // particles of the tile's own cells
+    static constexpr int kOwn = WIDE ? 256 : 160;
     // LDS capacity in particles: the workgroup stays under 40 KB so four
-    // workgroups (sixteen waves) fit a CU.
-    static constexpr int kCap = (DIM == 3) ? (POLY ? 1080 : 1456) : (POLY ? 1464 : 2168);
+    // workgroups (sixteen waves) fit a CU; the wide variant for denser grids
+    // stays under 60 KB (two workgroups a CU).
+    static constexpr int kCap = (DIM == 3) ? (POLY ? (WIDE ? 1632 : 1080) : (WIDE ? 2176 : 1456))
+                                           : (POLY ? 1464 : 2168);
 };
 
 struct TileLattice {
@@ -249,10 +240,9 @@ __device__ __forceinline__ bool trial_hits(const PassArgs &a, const double *sx, 
     return false;
 }
 
-template <int DIM, bool POLY>
-__global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
+template <int DIM, bool POLY, class C>
+__device__ __forceinline__ void tile_pass(const PassArgs &a, const TileLattice &L)
 {
-    using C = QuadCfg<DIM, POLY>;
     __shared__ double sx[C::kCap];
     __shared__ double sy[C::kCap];
     __shared__ double sz[DIM == 3 ? C::kCap : 1];
@@ -499,6 +489,19 @@ __global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
     }
 }
 
+template <int DIM, bool POLY>
+__global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
+{
+    tile_pass<DIM, POLY, QuadCfg<DIM, POLY>>(a, L);
+}
+
+// The same pass with a larger LDS region (denser grids, 3D).
+template <int DIM, bool POLY>
+__global__ void __launch_bounds__(256) k_migrate_tile_wide(PassArgs a, TileLattice L)
+{
+    tile_pass<DIM, POLY, QuadCfg<DIM, POLY, true>>(a, L);
+}
+
 // Tiles queued by k_migrate_tile because their neighbourhood exceeds LDS:
 // one thread per colour cell, candidates read from global memory.
 template <int DIM, bool POLY>
@@ -581,17 +584,6 @@ __device__ __forceinline__ bool platelet_hits(const PassArgs &a, const int32_t *
 }
 
 __device__ void migrate_platelet_cell(const PassArgs &a, int32_t cx, int32_t cy, int32_t cz);
-
-__global__ void __launch_bounds__(kBlock) k_migrate_platelet(PassArgs a, ColourLattice L)
-{
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= L.count) return;
-    const int32_t jx = t % L.h[0];
-    const int32_t r1 = t / L.h[0];
-    const int32_t jy = r1 % L.h[1];
-    const int32_t jz = r1 / L.h[1];
-    migrate_platelet_cell(a, 2 * jx + L.off[0], 2 * jy + L.off[1], 2 * jz + L.off[2]);
-}
 
 // Platelets on crowded grids: one 64-lane wavefront per colour cell, the
 // scheme of migrate_cell_wave.  A disk meets another only if their centres
@@ -941,6 +933,33 @@ bool wave_cells(int dim, const Grid &g, int32_t n)
     return (int64_t)n >= (int64_t)kWaveOccupancy * ncell;
 }
 
+namespace {
+
+// The tiled kernels stage a tile's (2T+1)^d region in LDS.  A grid takes
+// the standard kernel (0) while its mean region load stays below the LDS
+// capacity less five Poisson deviations, else the wide one (1, 3D) under
+// the same rule, else (2) one wavefront per cell: above that load most tiles
+// would fall back to the one-thread-per-cell global kernel.
+int tile_class(int dim, bool poly, const Grid &g, int32_t n)
+{
+    double cells = 1.0;
+    for (int ax = 0; ax < dim; ++ax) cells *= (double)g.na[ax];
+    auto fits = [&](double region, double cap) {
+        return (double)n / cells * region <= cap - 5.0 * sqrt(cap);
+    };
+    if (dim == 3) {
+        constexpr double region = QuadCfg<3, false>::kCells;
+        if (fits(region, poly ? QuadCfg<3, true>::kCap : QuadCfg<3, false>::kCap)) return 0;
+        if (fits(region, poly ? QuadCfg<3, true, true>::kCap : QuadCfg<3, false, true>::kCap))
+            return 1;
+        return 2;
+    }
+    constexpr double region = QuadCfg<2, false>::kCells;
+    return fits(region, poly ? QuadCfg<2, true>::kCap : QuadCfg<2, false>::kCap) ? 0 : 2;
+}
+
+}  // namespace
+
 hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int colour,
                           hipStream_t stream, bool *launched, hipEvent_t after_main, int *which)
 {
@@ -952,20 +971,16 @@ hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int 
         if (which) *which = kind;
         *launched = true;
     };
-    if (shape != SRM_PLATELET && wave_cells(dim, a.g, a.n)) {
-        const dim3 grid(L.count), block(64);
-        if (dim == 3) {
-            if (poly) hipLaunchKernelGGL((k_migrate_wave<3, true>), grid, block, 0, stream, a, L);
-            else hipLaunchKernelGGL((k_migrate_wave<3, false>), grid, block, 0, stream, a, L);
-        } else {
-            if (poly) hipLaunchKernelGGL((k_migrate_wave<2, true>), grid, block, 0, stream, a, L);
-            else hipLaunchKernelGGL((k_migrate_wave<2, false>), grid, block, 0, stream, a, L);
-        }
-        main_done(SRM_KERNEL_WAVE);
-        return hipGetLastError();
-    }
-    if (shape != SRM_PLATELET && a.ovf && tile_ok(dim, a.g)) {
-        TileLattice T{};
+    // Sparse ball grids large enough to tile run the LDS-tiled kernels
+    // (standard or wide region by the mean load).  Grids too small to tile
+    // have few cells per colour phase, where one thread per cell would leave
+    // the chip idle behind chains of dependent global loads: they, crowded
+    // grids and platelets run one wavefront per cell.
+    bool use_tile = shape != SRM_PLATELET && a.ovf && tile_ok(dim, a.g) && !wave_cells(dim, a.g, a.n);
+    int tclass = 0;
+    TileLattice T{};
+    if (use_tile) {
+        tclass = tile_class(dim, poly, a.g, a.n);
         const int tsz = (dim == 3) ? 4 : 8;
         T.tiles = 1;
         for (int ax = 0; ax < 3; ++ax) {
@@ -974,50 +989,48 @@ hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int 
             T.nt[ax] = (ax < dim) ? (L.h[ax] + tsz - 1) / tsz : 1;
             T.tiles *= T.nt[ax];
         }
-        if (T.tiles <= a.ovf_max_tiles) {
-            T.per_xcd = (T.tiles + 7) / 8;
-            T.colour = colour;
-            T.ovf = a.ovf;
-            T.max_tiles = a.ovf_max_tiles;
-            const dim3 grid(8 * T.per_xcd), block(256);
-            const dim3 ogrid(T.tiles < 512 ? T.tiles : 512), oblock(64);
-            if (dim == 3) {
-                if (poly) hipLaunchKernelGGL((k_migrate_tile<3, true>), grid, block, 0, stream, a, T);
-                else hipLaunchKernelGGL((k_migrate_tile<3, false>), grid, block, 0, stream, a, T);
-            } else {
-                if (poly) hipLaunchKernelGGL((k_migrate_tile<2, true>), grid, block, 0, stream, a, T);
-                else hipLaunchKernelGGL((k_migrate_tile<2, false>), grid, block, 0, stream, a, T);
-            }
-            main_done(SRM_KERNEL_TILE);
-            // tiles whose neighbourhood did not fit LDS
-            if (dim == 3) {
-                if (poly) hipLaunchKernelGGL((k_migrate_overflow<3, true>), ogrid, oblock, 0, stream, a, T);
-                else hipLaunchKernelGGL((k_migrate_overflow<3, false>), ogrid, oblock, 0, stream, a, T);
-            } else {
-                if (poly) hipLaunchKernelGGL((k_migrate_overflow<2, true>), ogrid, oblock, 0, stream, a, T);
-                else hipLaunchKernelGGL((k_migrate_overflow<2, false>), ogrid, oblock, 0, stream, a, T);
-            }
-            return hipGetLastError();
-        }
+        use_tile = tclass < 2 && T.tiles <= a.ovf_max_tiles;
     }
-    const dim3 grid(blocks_for(L.count)), block(kBlock);
-    if (shape == SRM_PLATELET) {
-        if (wave_cells(dim, a.g, a.n)) {
-            hipLaunchKernelGGL(k_migrate_platelet_wave, dim3(L.count), dim3(64), 0, stream, a, L);
-            main_done(SRM_KERNEL_PLATELET | SRM_KERNEL_WAVE);
+    if (use_tile) {
+        T.per_xcd = (T.tiles + 7) / 8;
+        T.colour = colour;
+        T.ovf = a.ovf;
+        T.max_tiles = a.ovf_max_tiles;
+        const dim3 grid(8 * T.per_xcd), block(256);
+        const dim3 ogrid(T.tiles < 512 ? T.tiles : 512), oblock(64);
+        if (dim == 3 && tclass == 1) {
+            if (poly) hipLaunchKernelGGL((k_migrate_tile_wide<3, true>), grid, block, 0, stream, a, T);
+            else hipLaunchKernelGGL((k_migrate_tile_wide<3, false>), grid, block, 0, stream, a, T);
+        } else if (dim == 3) {
+            if (poly) hipLaunchKernelGGL((k_migrate_tile<3, true>), grid, block, 0, stream, a, T);
+            else hipLaunchKernelGGL((k_migrate_tile<3, false>), grid, block, 0, stream, a, T);
         } else {
-            hipLaunchKernelGGL(k_migrate_platelet, grid, block, 0, stream, a, L);
-            main_done(SRM_KERNEL_PLATELET);
+            if (poly) hipLaunchKernelGGL((k_migrate_tile<2, true>), grid, block, 0, stream, a, T);
+            else hipLaunchKernelGGL((k_migrate_tile<2, false>), grid, block, 0, stream, a, T);
         }
-    } else {
+        main_done(tclass == 1 ? SRM_KERNEL_TILE_WIDE : SRM_KERNEL_TILE);
+        // tiles whose neighbourhood did not fit LDS
         if (dim == 3) {
-            if (poly) hipLaunchKernelGGL((k_migrate_ball<3, true>), grid, block, 0, stream, a, L);
-            else hipLaunchKernelGGL((k_migrate_ball<3, false>), grid, block, 0, stream, a, L);
+            if (poly) hipLaunchKernelGGL((k_migrate_overflow<3, true>), ogrid, oblock, 0, stream, a, T);
+            else hipLaunchKernelGGL((k_migrate_overflow<3, false>), ogrid, oblock, 0, stream, a, T);
         } else {
-            if (poly) hipLaunchKernelGGL((k_migrate_ball<2, true>), grid, block, 0, stream, a, L);
-            else hipLaunchKernelGGL((k_migrate_ball<2, false>), grid, block, 0, stream, a, L);
+            if (poly) hipLaunchKernelGGL((k_migrate_overflow<2, true>), ogrid, oblock, 0, stream, a, T);
+            else hipLaunchKernelGGL((k_migrate_overflow<2, false>), ogrid, oblock, 0, stream, a, T);
         }
-        main_done(SRM_KERNEL_CELL);
+        return hipGetLastError();
+    }
+    const dim3 grid(L.count), block(64);
+    if (shape == SRM_PLATELET) {
+        hipLaunchKernelGGL(k_migrate_platelet_wave, grid, block, 0, stream, a, L);
+        main_done(SRM_KERNEL_PLATELET | SRM_KERNEL_WAVE);
+    } else if (dim == 3) {
+        if (poly) hipLaunchKernelGGL((k_migrate_wave<3, true>), grid, block, 0, stream, a, L);
+        else hipLaunchKernelGGL((k_migrate_wave<3, false>), grid, block, 0, stream, a, L);
+        main_done(SRM_KERNEL_WAVE);
+    } else {
+        if (poly) hipLaunchKernelGGL((k_migrate_wave<2, true>), grid, block, 0, stream, a, L);
+        else hipLaunchKernelGGL((k_migrate_wave<2, false>), grid, block, 0, stream, a, L);
+        main_done(SRM_KERNEL_WAVE);
     }
     return hipGetLastError();
 }

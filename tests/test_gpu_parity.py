@@ -129,9 +129,11 @@ def test_single_pass_parity(srm, oracle_lib, dim, n, f, kind):
 
 # ------------------------------------------------------------------- sweeps
 
-def _sweep_parity(srm, oracle_lib, w, max_sweeps, every=1, **over):
+def _sweep_parity(srm, oracle_lib, w, max_sweeps, every=1, profile=False, **over):
     o = oracle_lib.Oracle.from_workload(w, **over)
     g = srm.SRM.from_workload(w, **over)
+    if profile:
+        g.profile(True)
     sweeps = 0
     while o.s < w.s_target and sweeps < max_sweeps:
         io, acc_o = o.sweep()
@@ -184,6 +186,20 @@ def test_crowded_cells_bitexact(srm, oracle_lib, dim, n, seed, f, sigma):
     grid = g.grid(w.s_target)[:dim]
     assert n >= 8 * int(np.prod(grid)), grid
     _say(f"crowded {dim}D: {sweeps} sweeps, final grid {grid}")
+    g.close()
+
+
+@pytest.mark.parametrize("sigma,seed,f,bits", [(None, 71, 0.35, 1 | 16), (0.05, 5, 0.25, 1 | 16 | 2)])
+def test_tile_variants_bitexact(srm, oracle_lib, sigma, seed, f, bits):
+    """The grid's mean occupancy picks the migration kernel: the standard
+    LDS tile (bit 1), the wide tile (16) as the region load nears the
+    standard capacity, then one wavefront per cell (2).  Runs that pass
+    through them equal the oracle sweep by sweep."""
+    kw = {} if sigma is None else dict(polydisperse_sigma=sigma)
+    w = _mk(3, 20000, seed, f, **kw)
+    o, g, sweeps = _sweep_parity(srm, oracle_lib, w, 1000, every=4, profile=True)
+    assert o.s == w.s_target
+    assert g.profile()["main_kernels"] == bits
     g.close()
 
 

@@ -164,6 +164,7 @@ def test_srm_from_rsa_start_matches_oracle(srm):
     assert np.array_equal(start["pos"], ref[1])
     o = oracle.Oracle.from_workload(w, pos=ref[1], s0=r0)
     g = srm.SRM.from_workload(w, pos=start["pos"], s0=r0)
+    g.profile(True)
     sweeps = 0
     while o.s < w.s_target and sweeps < 300:
         io, acc_o = o.sweep()
@@ -172,5 +173,8 @@ def test_srm_from_rsa_start_matches_oracle(srm):
         assert ig["committed"] == io["committed"] and ig["s"] == o.s, sweeps
     pos, _, s, t = g.state()
     assert np.array_equal(pos, o.soa()) and s == o.s == w.s_target
+    # the sparse early grids run the standard tile, 14^3 (1.8 particles a
+    # cell) the wide tile, the crowded final 12^3 one wavefront per cell
+    assert g.profile()["main_kernels"] == 1 | 2 | 16
     _say(f"RSA f0=0.1 -> SRM f=0.4: {sweeps} sweeps")
     g.close()
