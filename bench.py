@@ -146,7 +146,7 @@ def batched_extra(max_sweeps):
 
     ws = [srm_inputs.make_member(m) for m in srm_inputs.batch_members()]
     t0 = time.perf_counter()
-    shape = autotune(ws, sweeps=40, slots=(2, 4, 8), blocks=(128,), wave_occupancy=(2, 3, 6))
+    shape = autotune(ws, sweeps=40, slots=(2, 4, 8), blocks=(128,), wave_occupancy=(1, 2, 3))
     tune_s = time.perf_counter() - t0
     _say(f"batch autotune -> slots={shape[0]} block={shape[1]} wave={shape[2]} ({tune_s:.1f} s)")
     b = Batch(ws)
@@ -295,9 +295,9 @@ def platelet_protocol_extra(densities=(1.0, 2.0, 5.0), n=20_000, relax_sweeps=10
     (aspect ratio 100) at number density rho = N D^3 / L^3, grown with a
     larger swelling rate (c_w = 0.02, twice the default, with c_m = 0.1 a_t;
     smaller migration steps jam the run far below the target), then relaxed
-    with zero swelling
-    and a large migration step (c_m = 0.5 a_t) for `relax_sweeps` sweeps;
-    the critical percolation distance delta_c / D of both states (30
+    with zero swelling and a large migration step (c_m = 0.5 a_t) for
+    `relax_sweeps` sweeps; the critical percolation distance delta_c / D of
+    both states and of an RSA configuration at the same density (30
     bisection steps on the tunnelling gap)."""
     import math
 
@@ -339,12 +339,25 @@ def platelet_protocol_extra(densities=(1.0, 2.0, 5.0), n=20_000, relax_sweeps=10
         rel = gap_c(r, diam)
         overlaps = len(r.pairs(0.0))
         r.close()
+        # the RSA configuration at the same number density (Fig. 9's reference)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        start = srm.rsa(3, srm.PLATELET, n, (1.0, 1.0, 1.0), w.s_target, w.seed)
+        t_rsa = time.perf_counter() - t0
+        q = srm.SRM(dim=3, n=n, s_target=w.s_target, c_w=0.0, c_m=c_m, n_k=8, n_l=8,
+                    seed=w.seed, pos=start["pos"], normals=start["normals"], shape=srm.PLATELET,
+                    c_n=c_m / w.s_target, thick_ratio=w.thick_ratio, s0=w.s_target)
+        rsa = gap_c(q, diam)
+        q.close()
         rows.append({"rho": rho, "f": f, "converged": st == 0, "grow_sweeps": info["sweeps"],
                      "grow_s": t_hoc, "relax_s": t_rel, "delta_c_over_d_grown": hoc,
-                     "delta_c_over_d_relaxed": rel, "overlapping_pairs": overlaps})
+                     "delta_c_over_d_relaxed": rel, "overlapping_pairs": overlaps,
+                     "rsa_s": t_rsa, "rsa_candidates": start["drawn"],
+                     "delta_c_over_d_rsa": rsa})
         _say(f"platelet protocol: {rows[-1]}")
     return {"workload": f"{n} platelets, aspect ratio 100, seed 11; grown: c_w 0.02, c_m 0.1 a_t; "
-                        f"relax: c_w 0, c_m 0.5 a_t, {relax_sweeps} sweeps", "runs": rows}
+                        f"relax: c_w 0, c_m 0.5 a_t, {relax_sweeps} sweeps; RSA at the same "
+                        f"density", "runs": rows}
 
 def grad_extra(steps, steer_steps):
     """Soft g(r) (64 Gaussian bins up to 5r) + overlap energy, forward and
