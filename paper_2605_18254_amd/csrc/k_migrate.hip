@@ -240,6 +240,47 @@ __device__ __forceinline__ bool trial_hits(const PassArgs &a, const double *sx, 
     return false;
 }
 
+// Does trial position y meet a candidate of the near list (other cells only)?
+template <int DIM, bool POLY, bool GENERAL>
+__device__ __forceinline__ bool near_hits(const PassArgs &a, const double *sx, const double *sy,
+                                          const double *sz, const double *srho,
+                                          const uint16_t *nl, int32_t nn, double yx, double yy,
+                                          double yz, double Ri)
+{
+    for (int32_t e = 0; e < nn; ++e) {
+        const int32_t c = nl[e];
+        const double qq = sq_dist<DIM, GENERAL>(a.g, yx, yy, yz, sx[c], sy[c],
+                                                (DIM == 3) ? sz[c] : 0.0);
+        double sig2;
+        if (POLY) {
+            const double sig = Ri + a.s * srho[c];
+            sig2 = sig * sig;
+        } else {
+            sig2 = a.sig2_mono;
+        }
+        if (qq <= sig2) return true;
+    }
+    return false;
+}
+
+// Does trial position y meet the particle in LDS slot c?
+template <int DIM, bool POLY, bool GENERAL>
+__device__ __forceinline__ bool slot_hit(const PassArgs &a, const double *sx, const double *sy,
+                                         const double *sz, const double *srho, int32_t c,
+                                         double yx, double yy, double yz, double Ri)
+{
+    const double qq = sq_dist<DIM, GENERAL>(a.g, yx, yy, yz, sx[c], sy[c],
+                                            (DIM == 3) ? sz[c] : 0.0);
+    double sig2;
+    if (POLY) {
+        const double sig = Ri + a.s * srho[c];
+        sig2 = sig * sig;
+    } else {
+        sig2 = a.sig2_mono;
+    }
+    return qq <= sig2;
+}
+
 template <int DIM, bool POLY, class C>
 __device__ __forceinline__ void tile_pass(const PassArgs &a, const TileLattice &L)
 {
@@ -435,57 +476,144 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, const TileLattice &
     const bool general = !is_interior<DIM>(a.g, cx, cy, cz);
     const int32_t o0 = obase[q];
 
-    for (int32_t p = ob; p < oe; ++p) {
-        const int32_t gp = gb + (p - ob);
-        const int32_t o = o0 + (p - ob);
-        const double px = sx[p], py = sy[p], pz = (DIM == 3) ? sz[p] : 0.0;
-        const double Ri = POLY ? a.s * srho[p] : a.s;
-        const int32_t nn = use_near ? (ncnt[o] > C::kNear ? 255 : ncnt[o]) : 255;
-        const uint16_t *nl = use_near ? nearl[o] : nullptr;
-        const uint32_t id = (uint32_t)a.buf.id[gp];
-        uint8_t code = 0;
-        Draw d = a.draw;
-        for (int32_t base = 1; base <= a.n_l; base += 4) {
-            const int32_t l = base + sub;
-            bool free_ = false;
-            double yx = 0.0, yy = 0.0, yz = 0.0;
-            if (l <= a.n_l) {
-                double v[3];
-                d.word = a.draw.word | ((uint32_t)l << 8);
-                unit_vector<DIM>(d, id, 0, a.c_m, v);
-                yx = wrap_coord(px + v[0], a.g.box[0]);
-                yy = wrap_coord(py + v[1], a.g.box[1]);
-                yz = (DIM == 3) ? wrap_coord(pz + v[2], a.g.box[2]) : 0.0;
-                const bool hit =
-                    general ? trial_hits<DIM, POLY, true>(a, sx, sy, sz, srho, lst, nl, nn, rx, ry,
-                                                          rz, ob, oe, p, yx, yy, yz, Ri)
-                            : trial_hits<DIM, POLY, false>(a, sx, sy, sz, srho, lst, nl, nn, rx,
-                                                           ry, rz, ob, oe, p, yx, yy, yz, Ri);
-                free_ = !hit;
-            }
-            const uint32_t fb = quad_bits(__ballot(free_));
-            if (fb) {
-                const int win = __ffs(fb) - 1;
-                if (sub == win) {
-                    sx[p] = yx;
-                    sy[p] = yy;
-                    if (DIM == 3) sz[p] = yz;
-                    a.buf.x[0][gp] = yx;
-                    a.buf.x[1][gp] = yy;
-                    if (DIM == 3) a.buf.x[2][gp] = yz;
+    // Groups of up to four particles of the cell.  The near list holds only
+    // other cells' particles, which no lane moves during this colour phase,
+    // so lane `sub` first finds, for particle g0 + sub, its first trial that
+    // meets no near-list candidate (trials before it are rejected whatever
+    // the cell mates do).  Then the group is settled in id order: that trial
+    // is accepted if it also misses the cell mates at their current
+    // positions; otherwise (or without a near list) the quad tests the
+    // remaining trials four at a time against the whole neighbourhood.
+    // Either way each particle takes its first free trial, in id order.
+    for (int32_t g0 = ob; g0 < oe; g0 += 4) {
+        const int32_t ps = g0 + sub;
+        bool spec = false;
+        int32_t l1 = 0;  // first near-free trial of particle ps (0: none)
+        double sx1 = 0.0, sy1 = 0.0, sz1 = 0.0;
+        if (ps < oe) {
+            const int32_t o = o0 + (ps - ob);
+            if (use_near && ncnt[o] <= C::kNear) {
+                spec = true;
+                const int32_t nn = ncnt[o];
+                const double px = sx[ps], py = sy[ps], pz = (DIM == 3) ? sz[ps] : 0.0;
+                const double Ri = POLY ? a.s * srho[ps] : a.s;
+                const uint32_t id = (uint32_t)a.buf.id[gb + (ps - ob)];
+                Draw d = a.draw;
+                for (int32_t l = 1; l <= a.n_l; ++l) {
+                    double v[3];
+                    d.word = a.draw.word | ((uint32_t)l << 8);
+                    unit_vector<DIM>(d, id, 0, a.c_m, v);
+                    const double yx = wrap_coord(px + v[0], a.g.box[0]);
+                    const double yy = wrap_coord(py + v[1], a.g.box[1]);
+                    const double yz = (DIM == 3) ? wrap_coord(pz + v[2], a.g.box[2]) : 0.0;
+                    const bool hit =
+                        general ? near_hits<DIM, POLY, true>(a, sx, sy, sz, srho, nearl[o], nn, yx,
+                                                             yy, yz, Ri)
+                                : near_hits<DIM, POLY, false>(a, sx, sy, sz, srho, nearl[o], nn,
+                                                              yx, yy, yz, Ri);
+                    if (!hit) {
+                        l1 = l;
+                        sx1 = yx;
+                        sy1 = yy;
+                        sz1 = yz;
+                        break;
+                    }
                 }
-                code = (uint8_t)(base + win);
-                break;
             }
         }
-        if (sub == 0) {
-            a.acc[gp] = code;
-            if (code == 0) a.failed[1 + atomicAdd(&a.failed[0], 1)] = gp;
+        const int32_t gend = (oe - g0 < 4) ? oe : g0 + 4;
+        for (int32_t p = g0; p < gend; ++p) {
+            const int32_t src = (tid & 63 & ~3) | (p - g0);
+            const bool sp = __shfl((int)spec, src, 64) != 0;
+            const int32_t lp = __shfl(l1, src, 64);
+            const double qx = __shfl(sx1, src, 64);
+            const double qy = __shfl(sy1, src, 64);
+            const double qz = __shfl(sz1, src, 64);
+            const int32_t gp = gb + (p - ob);
+            const double Ri = POLY ? a.s * srho[p] : a.s;
+            uint8_t code = 0;
+            int32_t first = 1;
+            bool done = false;
+            if (sp) {
+                if (lp == 0) {
+                    done = true;  // every trial meets the near list
+                } else {
+                    bool hit = false;
+                    for (int32_t c = ob + sub; c < oe; c += 4) {
+                        if (c == p) continue;
+                        hit = hit || (general ? slot_hit<DIM, POLY, true>(a, sx, sy, sz, srho, c,
+                                                                          qx, qy, qz, Ri)
+                                              : slot_hit<DIM, POLY, false>(a, sx, sy, sz, srho, c,
+                                                                           qx, qy, qz, Ri));
+                    }
+                    if (quad_bits(__ballot(hit)) == 0) {
+                        done = true;
+                        code = (uint8_t)lp;
+                        if (sub == 0) {
+                            sx[p] = qx;
+                            sy[p] = qy;
+                            if (DIM == 3) sz[p] = qz;
+                            a.buf.x[0][gp] = qx;
+                            a.buf.x[1][gp] = qy;
+                            if (DIM == 3) a.buf.x[2][gp] = qz;
+                        }
+                    } else {
+                        first = lp + 1;
+                    }
+                }
+            }
+            if (!done) {
+                const int32_t o = o0 + (p - ob);
+                const double px = sx[p], py = sy[p], pz = (DIM == 3) ? sz[p] : 0.0;
+                const int32_t nn = use_near ? (ncnt[o] > C::kNear ? 255 : ncnt[o]) : 255;
+                const uint16_t *nl = use_near ? nearl[o] : nullptr;
+                const uint32_t id = (uint32_t)a.buf.id[gp];
+                Draw d = a.draw;
+                for (int32_t base = first; base <= a.n_l; base += 4) {
+                    const int32_t l = base + sub;
+                    bool free_ = false;
+                    double yx = 0.0, yy = 0.0, yz = 0.0;
+                    if (l <= a.n_l) {
+                        double v[3];
+                        d.word = a.draw.word | ((uint32_t)l << 8);
+                        unit_vector<DIM>(d, id, 0, a.c_m, v);
+                        yx = wrap_coord(px + v[0], a.g.box[0]);
+                        yy = wrap_coord(py + v[1], a.g.box[1]);
+                        yz = (DIM == 3) ? wrap_coord(pz + v[2], a.g.box[2]) : 0.0;
+                        const bool hit =
+                            general ? trial_hits<DIM, POLY, true>(a, sx, sy, sz, srho, lst, nl, nn,
+                                                                  rx, ry, rz, ob, oe, p, yx, yy,
+                                                                  yz, Ri)
+                                    : trial_hits<DIM, POLY, false>(a, sx, sy, sz, srho, lst, nl,
+                                                                   nn, rx, ry, rz, ob, oe, p, yx,
+                                                                   yy, yz, Ri);
+                        free_ = !hit;
+                    }
+                    const uint32_t fb = quad_bits(__ballot(free_));
+                    if (fb) {
+                        const int win = __ffs(fb) - 1;
+                        if (sub == win) {
+                            sx[p] = yx;
+                            sy[p] = yy;
+                            if (DIM == 3) sz[p] = yz;
+                            a.buf.x[0][gp] = yx;
+                            a.buf.x[1][gp] = yy;
+                            if (DIM == 3) a.buf.x[2][gp] = yz;
+                        }
+                        code = (uint8_t)(base + win);
+                        break;
+                    }
+                }
+            }
+            if (sub == 0) {
+                a.acc[gp] = code;
+                if (code == 0) a.failed[1 + atomicAdd(&a.failed[0], 1)] = gp;
+            }
+            // the accepted position in LDS must be seen by the next particle
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        // the winner's LDS store must be seen by the quad's next particle
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -937,15 +1065,16 @@ namespace {
 
 // The tiled kernels stage a tile's (2T+1)^d region in LDS.  A grid takes
 // the standard kernel (0) while its mean region load stays below the LDS
-// capacity less five Poisson deviations, else the wide one (1, 3D) under
-// the same rule, else (2) one wavefront per cell: above that load most tiles
-// would fall back to the one-thread-per-cell global kernel.
+// capacity less three Poisson deviations (the counts of a dense hard-sphere
+// configuration fluctuate far less than Poisson's), else the wide one (1,
+// 3D) under the same rule, else (2) one wavefront per cell: above that load
+// many tiles would fall back to the one-thread-per-cell global kernel.
 int tile_class(int dim, bool poly, const Grid &g, int32_t n)
 {
     double cells = 1.0;
     for (int ax = 0; ax < dim; ++ax) cells *= (double)g.na[ax];
     auto fits = [&](double region, double cap) {
-        return (double)n / cells * region <= cap - 5.0 * sqrt(cap);
+        return (double)n / cells * region <= cap - 3.0 * sqrt(cap);
     };
     if (dim == 3) {
         constexpr double region = QuadCfg<3, false>::kCells;

@@ -173,8 +173,8 @@ def test_srm_from_rsa_start_matches_oracle(srm):
         assert ig["committed"] == io["committed"] and ig["s"] == o.s, sweeps
     pos, _, s, t = g.state()
     assert np.array_equal(pos, o.soa()) and s == o.s == w.s_target
-    # the sparse early grids run the standard tile, 14^3 (1.8 particles a
-    # cell) the wide tile, the crowded final 12^3 one wavefront per cell
-    assert g.profile()["main_kernels"] == 1 | 2 | 16
+    # the sparse early grids (16^3, 14^3) run the tiled kernel, the crowded
+    # final 12^3 (2.9 particles a cell) one wavefront per cell
+    assert g.profile()["main_kernels"] == 1 | 2
     _say(f"RSA f0=0.1 -> SRM f=0.4: {sweeps} sweeps")
     g.close()
