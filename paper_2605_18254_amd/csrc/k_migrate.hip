@@ -731,6 +731,8 @@ struct PlateLds {
     PlateOwn own[kPlateOwn];
     int32_t nn[kPlateOwn];
     int32_t near[kPlateOwn * kPlateNear];  // slot q >= 0, or -(k + 1) for own particle k
+    int32_t nfail;
+    int32_t fail[kPlateOwn];  // own indices that rejected every trial
 };
 
 // Trial l of a platelet: centre (stream 0, length c_m, wrapped) and normal
@@ -870,6 +872,7 @@ __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, Colour
         S.own[k] = o;
         S.nn[k] = 0;
     }
+    if (lane == 0) S.nfail = 0;
     __syncthreads();
     // A. near lists on centre distance
 #pragma unroll
@@ -986,9 +989,23 @@ __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, Colour
                 a.buf.nrm[2][p] = v2;
             }
             a.acc[p] = (uint8_t)code;
-            if (code == 0) a.failed[1 + atomicAdd(&a.failed[0], 1)] = p;
+            if (code == 0) S.fail[S.nfail++] = k;
         }
-        __syncthreads();
+        // The workgroup is this one wavefront, whose LDS operations complete
+        // in order: lane 0's stores only need to be ordered before the next
+        // particle's loads (a workgroup barrier would also wait for its
+        // global stores on every particle).
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // the cell's failures go to the global list once, off the chain
+    const int32_t nf = S.nfail;
+    if (nf > 0) {
+        int32_t base = 0;
+        if (lane == 0) base = atomicAdd(&a.failed[0], nf);
+        base = __shfl(base, 0, 64);
+        for (int32_t i = lane; i < nf; i += 64) a.failed[1 + base + i] = beg + S.fail[i];
     }
 }
 

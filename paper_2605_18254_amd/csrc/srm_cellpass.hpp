@@ -128,11 +128,14 @@ __device__ __forceinline__ bool check_ball_one(const PassArgs &a, int32_t p)
 //     position), and the cell's other particles within R_i + R_j + 3 c_m
 //     (each moves at most c_m before i's turn; the extra c_m is slack for
 //     rounding).  Lanes split the candidates.
-//  B. particles in ascending id order: the lanes split (trial, near entry)
-//     pairs of a group of consecutive trials, reading the cell's particles
-//     at their current LDS positions, and the lowest collision-free trial of
-//     the group wins -- the first free trial of the sequential rule, since
-//     no trial of one particle changes what another trial of it sees.
+//  B. first, in parallel, each particle's first trial that misses its
+//     near-list candidates outside the cell (fixed during the phase); then
+//     particles in ascending id order: that trial wins if it also misses
+//     the cell mates at their current LDS positions, else the lanes split
+//     (trial, near entry) pairs of a group of the following trials and the
+//     lowest collision-free trial of the group wins -- the first free trial
+//     of the sequential rule, since no trial of one particle changes what
+//     another trial of it sees.
 // A particle whose near list overflows tests its trials one at a time
 // against the whole stencil; a cell with more than kWaveOwn particles runs
 // on one lane with the global-memory routine above.
@@ -281,34 +284,81 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
         }
     }
     __syncthreads();
-    // B. the sequential part.  A lane's near-list candidate outside the cell
-    // does not move in this phase, so it is fetched one particle ahead (its
-    // load overlaps the current particle's work); cell mates are read from
-    // LDS at test time.
-    auto fetch = [&](int32_t kk, double &fx, double &fy, double &fz, double &fr) {
-        const int32_t mm = L.nn[kk];
-        if (mm < 1 || mm > kWaveNear) return;
-        const int32_t gg = lane / mm;
-        if (gg >= 64 / mm) return;
-        const int32_t ref = L.near[kk * kWaveNear + (lane - gg * mm)];
-        if (ref < 0) return;
-        fx = X[ref];
-        fy = Y[ref];
-        fz = (DIM == 3) ? Z[ref] : 0.0;
-        fr = POLY ? a.s * a.buf.rho[ref] : a.s;
-    };
-    double nx = 0.0, ny = 0.0, nz = 0.0, nr = 0.0;
-    fetch(0, nx, ny, nz, nr);
+    // B. the sequential part.  Cell mates are read from LDS at test time;
+    // near-list candidates outside the cell (fixed in this phase) are read
+    // from global memory only by the trials after a speculated one failed.
+    // B0. Lane j takes own particles j and j + 64 and finds each one's first
+    // trial that meets no near-list candidate outside the cell: those
+    // candidates do not move in this phase, so the trials before it are
+    // rejected whatever the cell mates do (-1: near list overflowed, not
+    // looked at; 0: every trial meets one).
+    int32_t spec[2] = {-1, -1};
+    double sxv[2] = {0.0, 0.0}, syv[2] = {0.0, 0.0}, szv[2] = {0.0, 0.0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int32_t k = lane + 64 * h;
+        if (k >= cnt || L.nn[k] > kWaveNear) continue;
+        const int32_t m = L.nn[k];
+        const WaveOwn me = L.own[k];
+        const uint32_t id = (uint32_t)L.id[k];
+        spec[h] = 0;
+        for (int32_t l = 1; l <= a.n_l; ++l) {
+            double yx, yy, yz;
+            wave_trial<DIM>(a, id, l, me.x, me.y, me.z, yx, yy, yz);
+            bool hit = false;
+            for (int32_t e = 0; e < m && !hit; ++e) {
+                const int32_t ref = L.near[k * kWaveNear + e];
+                if (ref >= 0)
+                    hit = wave_hit<DIM, POLY>(a, yx, yy, yz, me.r, X[ref], Y[ref],
+                                              (DIM == 3) ? Z[ref] : 0.0,
+                                              POLY ? a.s * a.buf.rho[ref] : a.s);
+            }
+            if (!hit) {
+                spec[h] = l;
+                sxv[h] = yx;
+                syv[h] = yy;
+                szv[h] = yz;
+                break;
+            }
+        }
+    }
     for (int32_t k = 0; k < cnt; ++k) {
         const int32_t p = beg + k;
         const WaveOwn me = L.own[k];
         const uint32_t id = (uint32_t)L.id[k];
         const int32_t m = L.nn[k];
-        const double qx = nx, qy = ny, qz = nz, qr = nr;
-        if (k + 1 < cnt) fetch(k + 1, nx, ny, nz, nr);
         int32_t code = 0;
         double wx = 0.0, wy = 0.0, wz = 0.0;
-        if (m == 0) {
+        // B1. settle the speculated trial against the cell mates at their
+        // current positions; on a hit the remaining trials follow below
+        const int h = k >> 6, src = k & 63;
+        const int32_t l1 = __shfl(h ? spec[1] : spec[0], src, 64);
+        int32_t first = 1;
+        bool done = false;
+        if (l1 == 0) {
+            done = true;
+        } else if (l1 > 0) {
+            const double tx = __shfl(h ? sxv[1] : sxv[0], src, 64);
+            const double ty = __shfl(h ? syv[1] : syv[0], src, 64);
+            const double tz = __shfl(h ? szv[1] : szv[0], src, 64);
+            bool hit = false;
+            for (int32_t j = lane; j < cnt; j += 64) {
+                if (j == k) continue;
+                const WaveOwn o = L.own[j];
+                hit = hit || wave_hit<DIM, POLY>(a, tx, ty, tz, me.r, o.x, o.y, o.z, o.r);
+            }
+            if (__ballot(hit) == 0) {
+                done = true;
+                code = l1;
+                wx = tx;
+                wy = ty;
+                wz = tz;
+            } else {
+                first = l1 + 1;
+            }
+        }
+        if (done) {
+        } else if (m == 0) {
             // nothing within reach: the first trial is free
             wave_trial<DIM>(a, id, 1, me.x, me.y, me.z, wx, wy, wz);
             code = (a.n_l >= 1) ? 1 : 0;
@@ -317,7 +367,14 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
             const int32_t g = lane / m, j = lane - g * m;
             const unsigned long long seg = (m == 64) ? ~0ull : ((1ull << m) - 1ull);
             const int32_t ref = L.near[k * kWaveNear + j];
-            for (int32_t l0 = 1; l0 <= a.n_l && code == 0; l0 += G) {
+            double qx = 0.0, qy = 0.0, qz = 0.0, qr = 0.0;
+            if (g < G && ref >= 0) {
+                qx = X[ref];
+                qy = Y[ref];
+                qz = (DIM == 3) ? Z[ref] : 0.0;
+                qr = POLY ? a.s * a.buf.rho[ref] : a.s;
+            }
+            for (int32_t l0 = first; l0 <= a.n_l && code == 0; l0 += G) {
                 const int32_t l = l0 + g;
                 const bool active = g < G && l <= a.n_l;
                 double yx, yy, yz;
@@ -348,7 +405,7 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
             }
         } else {
             // near list overflowed: the whole stencil, one trial at a time
-            for (int32_t l = 1; l <= a.n_l && code == 0; ++l) {
+            for (int32_t l = first; l <= a.n_l && code == 0; ++l) {
                 double yx, yy, yz;
                 wave_trial<DIM>(a, id, l, me.x, me.y, me.z, yx, yy, yz);
                 bool hit = false;
@@ -382,7 +439,13 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
             }
             a.acc[p] = (uint8_t)code;
         }
-        __syncthreads();
+        // The workgroup is this one wavefront, whose LDS operations complete
+        // in order: lane 0's stores only need to be ordered before the next
+        // particle's loads (a workgroup barrier here would also wait for the
+        // global stores on every particle).
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     // the cell's failures go to the global list once, off the chain
     const int32_t nf = L.nfail;
