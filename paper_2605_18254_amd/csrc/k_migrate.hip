@@ -659,6 +659,20 @@ __global__ void __launch_bounds__(64) k_migrate_overflow(PassArgs a, TileLattice
 // position and every later one at a position it kept if it was rejected).
 // So only particles with accept code 0 are tested; check_all tests every
 // particle (initial-state validation).
+// The same check with one wavefront per failed particle (crowded cells).
+template <int DIM, bool POLY>
+__global__ void __launch_bounds__(kBlock) k_check_ball_wave(PassArgs a, Counters *cnt)
+{
+    const int32_t count = a.failed[0];
+    const int lane = threadIdx.x & 63;
+    const int32_t waves = gridDim.x * (kBlock / 64);
+    for (int32_t i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); i < count; i += waves) {
+        if (__atomic_load_n(&cnt->overlap, __ATOMIC_RELAXED)) return;  // already known
+        if (check_ball_wave<DIM, POLY>(a, a.failed[1 + i], lane) && lane == 0)
+            atomicOr(&cnt->overlap, 1);
+    }
+}
+
 template <int DIM, bool POLY>
 __global__ void __launch_bounds__(kBlock) k_check_ball(PassArgs a, int32_t check_all, Counters *cnt)
 {
@@ -1185,6 +1199,18 @@ hipError_t check_overlaps(int dim, int shape, bool poly, const PassArgs &a, bool
                           Counters *cnt, hipStream_t stream)
 {
     if (a.n <= 0) return hipSuccess;
+    if (shape != SRM_PLATELET && !check_all && wave_cells(dim, a.g, a.n)) {
+        // crowded cells: one wavefront per failed particle
+        const unsigned wb = blocks_for(a.n) < 1024 ? blocks_for(a.n) : 1024;
+        if (dim == 3) {
+            if (poly) hipLaunchKernelGGL((k_check_ball_wave<3, true>), dim3(wb), dim3(kBlock), 0, stream, a, cnt);
+            else hipLaunchKernelGGL((k_check_ball_wave<3, false>), dim3(wb), dim3(kBlock), 0, stream, a, cnt);
+        } else {
+            if (poly) hipLaunchKernelGGL((k_check_ball_wave<2, true>), dim3(wb), dim3(kBlock), 0, stream, a, cnt);
+            else hipLaunchKernelGGL((k_check_ball_wave<2, false>), dim3(wb), dim3(kBlock), 0, stream, a, cnt);
+        }
+        return hipGetLastError();
+    }
     // grid-stride over the failed list (its length is only known on the device)
     const unsigned nb = blocks_for(a.n);
     const dim3 grid(check_all ? nb : (nb < 1024 ? nb : 1024)), block(kBlock);

@@ -378,19 +378,21 @@ __global__ void __launch_bounds__(64) k_bmigrate_wave(BatchDev d, int colour)
     }
 }
 
+// One wavefront per failed particle (grid-stride over the failed list).
 template <bool POLY>
 __global__ void __launch_bounds__(kB) k_bcheck(BatchDev d)
 {
     const int32_t count = d.failed[0];
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int32_t waves = gridDim.x * (kB / 64);
+    for (int32_t i = blockIdx.x * (kB / 64) + (threadIdx.x >> 6); i < count; i += waves) {
         const int32_t p = d.failed[1 + i];
         Rve &r = d.rve[d.rve_of[p]];
         if (__atomic_load_n(&r.overlap, __ATOMIC_RELAXED)) continue;  // already known
         const PassArgs a = pass_args_of(d, r);
-        const bool hit = (r.dim == 3) ? check_ball_one<3, POLY>(a, p)
-                                      : check_ball_one<2, POLY>(a, p);
-        if (hit) atomicOr(&r.overlap, 1);
+        const bool hit = (r.dim == 3) ? check_ball_wave<3, POLY>(a, p, lane)
+                                      : check_ball_wave<2, POLY>(a, p, lane);
+        if (hit && lane == 0) atomicOr(&r.overlap, 1);
     }
 }
 

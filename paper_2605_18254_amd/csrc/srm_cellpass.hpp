@@ -117,6 +117,49 @@ __device__ __forceinline__ bool check_ball_one(const PassArgs &a, int32_t p)
     return ball_hits<DIM, POLY, true>(a, lo, hi, p, x, y, z, Ri);
 }
 
+// Algorithm 6 for the particle in slot p, its stencil split over the 64
+// lanes of a wavefront (crowded cells hold tens of particles, so one lane's
+// scan would be a long chain of dependent loads): the same exact test as
+// check_ball_one, any lane's hit counts.
+template <int DIM, bool POLY>
+__device__ __forceinline__ bool check_ball_wave(const PassArgs &a, int32_t p, int lane)
+{
+    const double *__restrict__ X = a.buf.x[0];
+    const double *__restrict__ Y = a.buf.x[1];
+    const double *__restrict__ Z = a.buf.x[2];
+    const double x = X[p], y = Y[p];
+    const double z = (DIM == 3) ? Z[p] : 0.0;
+    const int32_t cx = cell_coord(x, a.g.inv_w[0], a.g.na[0]);
+    const int32_t cy = cell_coord(y, a.g.inv_w[1], a.g.na[1]);
+    const int32_t cz = (DIM == 3) ? cell_coord(z, a.g.inv_w[2], a.g.na[2]) : 0;
+    int32_t lo[Rows<DIM>::kRanges], hi[Rows<DIM>::kRanges];
+    stencil_slices<DIM>(a.g, a.start, cx, cy, cz, lo, hi);
+    const double Ri = POLY ? a.s * a.buf.rho[p] : a.s;
+    bool hit = false;
+#pragma unroll
+    for (int r = 0; r < Rows<DIM>::kRanges; ++r) {
+        for (int32_t q = lo[r] + lane; q < hi[r] && !hit; q += 64) {
+            if (q == p) continue;
+            const double dx = min_image(x - X[q], a.g.box[0], a.g.half[0]);
+            const double dy = min_image(y - Y[q], a.g.box[1], a.g.half[1]);
+            double qq = dx * dx + dy * dy;
+            if (DIM == 3) {
+                const double dz = min_image(z - Z[q], a.g.box[2], a.g.half[2]);
+                qq = qq + dz * dz;
+            }
+            double sig2;
+            if (POLY) {
+                const double sig = Ri + a.s * a.buf.rho[q];
+                sig2 = sig * sig;
+            } else {
+                sig2 = a.sig2_mono;
+            }
+            hit = qq <= sig2;
+        }
+    }
+    return __ballot(hit) != 0;
+}
+
 // ---- one wavefront per cell ------------------------------------------------
 //
 // For crowded cells (polydisperse boxes put tens of particles in a cell,
