@@ -734,17 +734,21 @@ __device__ void migrate_platelet_cell(const PassArgs &a, int32_t cx, int32_t cy,
 // lanes split (trial, near entry) pairs, each running the exact disk-disk
 // test with the lower id as disk 1.
 constexpr int kPlateOwn = 64;
-constexpr int kPlateNear = 32;
+// Near-list capacities: 32 entries, or 96 when large migration steps put
+// tens of disks within reach (chosen per pass on the host).
+constexpr int kPlateNearShort = 32;
+constexpr int kPlateNearLong = 96;
 
 struct PlateOwn {
     double x, y, z, a, n0, n1, n2;
     int32_t id, pad;
 };
 
+template <int NEAR>
 struct PlateLds {
     PlateOwn own[kPlateOwn];
     int32_t nn[kPlateOwn];
-    int32_t near[kPlateOwn * kPlateNear];  // slot q >= 0, or -(k + 1) for own particle k
+    int32_t near[kPlateOwn * NEAR];  // slot q >= 0, or -(k + 1) for own particle k
     int32_t nfail;
     int32_t fail[kPlateOwn];  // own indices that rejected every trial
 };
@@ -788,7 +792,8 @@ __device__ __forceinline__ bool plate_pair_hit(const PassArgs &a, int32_t self_i
     return disks_intersect(dx, dy, dz, nq, aj, ny, ai);
 }
 
-__device__ __forceinline__ bool plate_ref_hit(const PassArgs &a, const PlateLds &L, int32_t ref,
+template <class LDS>
+__device__ __forceinline__ bool plate_ref_hit(const PassArgs &a, const LDS &L, int32_t ref,
                                               int32_t self_id, const double y[3],
                                               const double ny[3], double ai)
 {
@@ -849,9 +854,10 @@ __device__ void migrate_platelet_cell(const PassArgs &a, int32_t cx, int32_t cy,
     }
 }
 
+template <int NEAR>
 __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, ColourLattice L)
 {
-    __shared__ PlateLds S;
+    __shared__ PlateLds<NEAR> S;
     const int lane = threadIdx.x;
     const int32_t t = blockIdx.x;
     const int32_t jx = t % L.h[0];
@@ -903,7 +909,7 @@ __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, Colour
                 const double dz = min_image(o.z - qz, a.g.box[2], a.g.half[2]);
                 if ((dx * dx + dy * dy) + dz * dz <= reach * reach) {
                     const int32_t slot = atomicAdd(&S.nn[k], 1);
-                    if (slot < kPlateNear) S.near[k * kPlateNear + slot] = q;
+                    if (slot < NEAR) S.near[k * NEAR + slot] = q;
                 }
             }
         }
@@ -919,7 +925,7 @@ __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, Colour
             const double dz = min_image(o.z - b.z, a.g.box[2], a.g.half[2]);
             if ((dx * dx + dy * dy) + dz * dz <= reach * reach) {
                 const int32_t slot = atomicAdd(&S.nn[k], 1);
-                if (slot < kPlateNear) S.near[k * kPlateNear + slot] = -(j + 1);
+                if (slot < NEAR) S.near[k * NEAR + slot] = -(j + 1);
             }
         }
     }
@@ -931,7 +937,8 @@ __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, Colour
         const int32_t m = S.nn[k];
         int32_t code = 0;
         double w0 = 0.0, w1 = 0.0, w2 = 0.0, v0 = 0.0, v1 = 0.0, v2 = 0.0;
-        if (m <= kPlateNear) {
+        // (trial, entry) groups while the list fits its capacity and the lanes
+        if (m <= (NEAR < 64 ? NEAR : 64)) {
             const int32_t mm = m > 0 ? m : 1;
             const int32_t G = 64 / mm;
             const int32_t g = lane / mm, j = lane - g * mm;
@@ -942,7 +949,7 @@ __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, Colour
                 double y[3], ny[3];
                 plate_trial(a, me, active ? l : l0, y, ny);
                 const bool hit = active && m > 0 &&
-                                 plate_ref_hit(a, S, S.near[k * kPlateNear + j], me.id, y, ny, me.a);
+                                 plate_ref_hit(a, S, S.near[k * NEAR + j], me.id, y, ny, me.a);
                 const unsigned long long hits = __ballot(hit);
                 int32_t win = -1;
                 for (int32_t gg = 0; gg < G && l0 + gg <= a.n_l; ++gg) {
@@ -959,6 +966,24 @@ __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, Colour
                     v0 = __shfl(ny[0], win * mm, 64);
                     v1 = __shfl(ny[1], win * mm, 64);
                     v2 = __shfl(ny[2], win * mm, 64);
+                }
+            }
+        } else if (m <= NEAR) {
+            // a long near list: one trial at a time, the lanes split the list
+            for (int32_t l = 1; l <= a.n_l && code == 0; ++l) {
+                double y[3], ny[3];
+                plate_trial(a, me, l, y, ny);
+                bool hit = false;
+                for (int32_t e = lane; e < m; e += 64)
+                    hit = hit || plate_ref_hit(a, S, S.near[k * NEAR + e], me.id, y, ny, me.a);
+                if (__ballot(hit) == 0) {
+                    code = l;
+                    w0 = y[0];
+                    w1 = y[1];
+                    w2 = y[2];
+                    v0 = ny[0];
+                    v1 = ny[1];
+                    v2 = ny[2];
                 }
             }
         } else {
@@ -1181,7 +1206,16 @@ hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int 
     }
     const dim3 grid(L.count), block(64);
     if (shape == SRM_PLATELET) {
-        hipLaunchKernelGGL(k_migrate_platelet_wave, grid, block, 0, stream, a, L);
+        // expected near-list length: centres within 2 s + 2 c_m at the mean
+        // density (s the radius scale; unequal platelets may overflow the
+        // short list, which only costs time)
+        const double reach = 2.0 * a.s + 2.0 * a.c_m;
+        const double vol = a.g.box[0] * a.g.box[1] * a.g.box[2];
+        const double expect = (double)a.n / vol * (4.0 / 3.0) * 3.141592653589793 * reach * reach * reach;
+        if (expect > 20.0)
+            hipLaunchKernelGGL((k_migrate_platelet_wave<kPlateNearLong>), grid, block, 0, stream, a, L);
+        else
+            hipLaunchKernelGGL((k_migrate_platelet_wave<kPlateNearShort>), grid, block, 0, stream, a, L);
         main_done(SRM_KERNEL_PLATELET | SRM_KERNEL_WAVE);
     } else if (dim == 3) {
         if (poly) hipLaunchKernelGGL((k_migrate_wave<3, true>), grid, block, 0, stream, a, L);

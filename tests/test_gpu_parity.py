@@ -257,6 +257,24 @@ def test_platelets_isotropic_passes(srm, oracle_lib):
     g.close()
 
 
+def test_platelets_large_steps_long_near_lists(srm, oracle_lib):
+    """Migration steps of half a platelet radius at number density 4 put
+    ~50 disks within reach of each one: the long near lists (and their
+    overflow path) against the oracle, sweep by sweep, then 10 relaxation
+    sweeps without swelling."""
+    w = srm_inputs.make("platelets", n=1500, seed=9, f_target=math.pi * 4.0 / 400.0, c_w=0.05,
+                        c_m_rel=0.5)
+    o, g, sweeps = _sweep_parity(srm, oracle_lib, w, 60, every=3)
+    g.close()
+    _say(f"platelets, large steps: {sweeps} sweeps, s/s_t={o.s / w.s_target}")
+    # no swelling (s stays below the nominal target), large steps
+    o2, g2, n2 = _sweep_parity(srm, oracle_lib, w, 10, every=1, pos=o.soa(), s0=o.s, sweep0=o.t,
+                               normals=np.ascontiguousarray(o.nrm.T), c_w=0.0,
+                               s_target=1.5 * w.s_target)
+    assert n2 == 10 and o2.s == o.s
+    g2.close()
+
+
 # --------------------------------------------------------------- edge cases
 
 def test_single_particle_and_tiny_systems(srm, oracle_lib):
