@@ -504,7 +504,8 @@ def main():
     # the colour phases' main kernel alone (the tiled kernel on this workload)
     avg_launch_s = prof["ms_migrate_main"] / 1e3 / launches
     main_name = {1: "k_migrate_tile<3,false>", 2: "k_migrate_wave<3,false>",
-                 16: "k_migrate_tile_wide<3,false>"}.get(prof["main_kernels"], "mixed")
+                 16: "k_migrate_tile_wide<3,false>",
+                 32: "k_migrate_tile_mid<3,false>"}.get(prof["main_kernels"], "mixed")
     traffic = recorded_traffic(main_name)
     upd_per_launch = updates / launches
     bytes_per_launch = ALG_BYTES_PER_UPDATE * upd_per_launch

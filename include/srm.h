@@ -345,7 +345,8 @@ typedef struct {
 #define SRM_KERNEL_WAVE 2     /* one wavefront per cell (crowded or small grids) */
 #define SRM_KERNEL_CELL 4     /* reserved: one thread per cell (not selected) */
 #define SRM_KERNEL_PLATELET 8 /* platelets (with SRM_KERNEL_WAVE) */
-#define SRM_KERNEL_TILE_WIDE 16 /* LDS-tiled with a larger region (denser 3D grids) */
+#define SRM_KERNEL_TILE_WIDE 16 /* LDS-tiled with the largest region (denser 3D grids) */
+#define SRM_KERNEL_TILE_MID 32  /* LDS-tiled with a middle region (3D) */
 
 /* Profiling switches, reset with the accumulated profile: bit 0 times the
  * phases above with hipEvents; bit 1 also counts trial moves (a small

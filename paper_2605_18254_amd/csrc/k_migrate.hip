@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(64) k_migrate_wave(PassArgs a, ColourLattice L
 // synchronisation in phase B.  A tile whose neighbourhood does not fit LDS
 // is queued for the global-memory kernel.
 
-template <int DIM, bool POLY, bool WIDE = false>
+template <int DIM, bool POLY, int V = 0>  // V: LDS region class 0 standard, 1 mid, 2 wide
 struct QuadCfg {
     static constexpr int T = (DIM == 3) ? 4 : 8;
     static constexpr int R = 2 * T + 1;
@@ -74,11 +74,12 @@ struct QuadCfg {
     static constexpr int kPer = (kCells + kThreads - 1) / kThreads;
     static constexpr int kNear = 11;    // near-list entries per particle
     // particles of the tile's own cells
-    static constexpr int kOwn = WIDE ? 256 : 160;
+    static constexpr int kOwn = (V == 2) ? 256 : (V == 1) ? 224 : 160;
     // LDS capacity in particles: the workgroup stays under 40 KB so four
     // workgroups (sixteen waves) fit a CU; the wide variant for denser grids
     // stays under 60 KB (two workgroups a CU).
-    static constexpr int kCap = (DIM == 3) ? (POLY ? (WIDE ? 1632 : 1080) : (WIDE ? 2176 : 1456))
+    static constexpr int kCap = (DIM == 3) ? (POLY ? ((V == 2) ? 1632 : (V == 1) ? 1320 : 1080)
+                                                   : ((V == 2) ? 2176 : (V == 1) ? 1744 : 1456))
                                            : (POLY ? 1464 : 2168);
 };
 
@@ -627,7 +628,14 @@ __global__ void __launch_bounds__(256) k_migrate_tile(PassArgs a, TileLattice L)
 template <int DIM, bool POLY>
 __global__ void __launch_bounds__(256) k_migrate_tile_wide(PassArgs a, TileLattice L)
 {
-    tile_pass<DIM, POLY, QuadCfg<DIM, POLY, true>>(a, L);
+    tile_pass<DIM, POLY, QuadCfg<DIM, POLY, 2>>(a, L);
+}
+
+// A middle region (3D, three workgroups a CU).
+template <int DIM, bool POLY>
+__global__ void __launch_bounds__(256) k_migrate_tile_mid(PassArgs a, TileLattice L)
+{
+    tile_pass<DIM, POLY, QuadCfg<DIM, POLY, 1>>(a, L);
 }
 
 // Tiles queued by k_migrate_tile because their neighbourhood exceeds LDS:
@@ -1122,9 +1130,10 @@ namespace {
 // The tiled kernels stage a tile's (2T+1)^d region in LDS.  A grid takes
 // the standard kernel (0) while its mean region load stays below the LDS
 // capacity less three Poisson deviations (the counts of a dense hard-sphere
-// configuration fluctuate far less than Poisson's), else the wide one (1,
-// 3D) under the same rule, else (2) one wavefront per cell: above that load
-// many tiles would fall back to the one-thread-per-cell global kernel.
+// configuration fluctuate far less than Poisson's), else the middle (1)
+// or the wide (2) region (3D) under the same rule, else (3) one wavefront
+// per cell: above that load many tiles would fall back to the
+// one-thread-per-cell global kernel.
 int tile_class(int dim, bool poly, const Grid &g, int32_t n)
 {
     double cells = 1.0;
@@ -1135,12 +1144,12 @@ int tile_class(int dim, bool poly, const Grid &g, int32_t n)
     if (dim == 3) {
         constexpr double region = QuadCfg<3, false>::kCells;
         if (fits(region, poly ? QuadCfg<3, true>::kCap : QuadCfg<3, false>::kCap)) return 0;
-        if (fits(region, poly ? QuadCfg<3, true, true>::kCap : QuadCfg<3, false, true>::kCap))
-            return 1;
-        return 2;
+        if (fits(region, poly ? QuadCfg<3, true, 1>::kCap : QuadCfg<3, false, 1>::kCap)) return 1;
+        if (fits(region, poly ? QuadCfg<3, true, 2>::kCap : QuadCfg<3, false, 2>::kCap)) return 2;
+        return 3;
     }
     constexpr double region = QuadCfg<2, false>::kCells;
-    return fits(region, poly ? QuadCfg<2, true>::kCap : QuadCfg<2, false>::kCap) ? 0 : 2;
+    return fits(region, poly ? QuadCfg<2, true>::kCap : QuadCfg<2, false>::kCap) ? 0 : 3;
 }
 
 }  // namespace
@@ -1174,7 +1183,7 @@ hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int 
             T.nt[ax] = (ax < dim) ? (L.h[ax] + tsz - 1) / tsz : 1;
             T.tiles *= T.nt[ax];
         }
-        use_tile = tclass < 2 && T.tiles <= a.ovf_max_tiles;
+        use_tile = tclass < 3 && T.tiles <= a.ovf_max_tiles;
     }
     if (use_tile) {
         T.per_xcd = (T.tiles + 7) / 8;
@@ -1183,9 +1192,12 @@ hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int 
         T.max_tiles = a.ovf_max_tiles;
         const dim3 grid(8 * T.per_xcd), block(256);
         const dim3 ogrid(T.tiles < 512 ? T.tiles : 512), oblock(64);
-        if (dim == 3 && tclass == 1) {
+        if (dim == 3 && tclass == 2) {
             if (poly) hipLaunchKernelGGL((k_migrate_tile_wide<3, true>), grid, block, 0, stream, a, T);
             else hipLaunchKernelGGL((k_migrate_tile_wide<3, false>), grid, block, 0, stream, a, T);
+        } else if (dim == 3 && tclass == 1) {
+            if (poly) hipLaunchKernelGGL((k_migrate_tile_mid<3, true>), grid, block, 0, stream, a, T);
+            else hipLaunchKernelGGL((k_migrate_tile_mid<3, false>), grid, block, 0, stream, a, T);
         } else if (dim == 3) {
             if (poly) hipLaunchKernelGGL((k_migrate_tile<3, true>), grid, block, 0, stream, a, T);
             else hipLaunchKernelGGL((k_migrate_tile<3, false>), grid, block, 0, stream, a, T);
@@ -1193,7 +1205,7 @@ hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int 
             if (poly) hipLaunchKernelGGL((k_migrate_tile<2, true>), grid, block, 0, stream, a, T);
             else hipLaunchKernelGGL((k_migrate_tile<2, false>), grid, block, 0, stream, a, T);
         }
-        main_done(tclass == 1 ? SRM_KERNEL_TILE_WIDE : SRM_KERNEL_TILE);
+        main_done(tclass == 2 ? SRM_KERNEL_TILE_WIDE : tclass == 1 ? SRM_KERNEL_TILE_MID : SRM_KERNEL_TILE);
         // tiles whose neighbourhood did not fit LDS
         if (dim == 3) {
             if (poly) hipLaunchKernelGGL((k_migrate_overflow<3, true>), ogrid, oblock, 0, stream, a, T);

@@ -90,33 +90,35 @@ def test_fullsize_dense_pass_matches_oracle_on_sample_blocks(srm, oracle_lib, wo
         del o
 
 
-def test_fullsize_wide_tile_pass_matches_oracle_on_sample_blocks(srm, oracle_lib, workload):
-    """The same comparison on a coarser 170^3 grid (about 2.04 particles a
-    cell, the density of the Fig. 2 protocol's late sweeps), where the
-    migration runs the wide LDS tile: sample blocks inside the box and
+@pytest.mark.parametrize("na,bits", [(170, 32), (160, 16)])
+def test_fullsize_larger_tiles_pass_matches_oracle_on_sample_blocks(srm, oracle_lib, workload,
+                                                                    na, bits):
+    """The same comparison on coarser grids: 170^3 (about 2.04 particles a
+    cell, the density of the Fig. 2 protocol's late sweeps) runs the middle
+    LDS region, 160^3 (2.44) the wide one; sample blocks inside the box and
     across the periodic corner equal the oracle."""
     w = workload
-    grid_s = (1.0 / 170.5 - 2.5 * w.c_m) / 2.5
+    grid_s = (1.0 / (na + 0.5) - 2.5 * w.c_m) / 2.5
     s = 0.7 * w.s_target
     g = srm.SRM.from_workload(w, device=True)
-    assert tuple(g.grid(grid_s)) == (170, 170, 170)
+    assert tuple(g.grid(grid_s)) == (na, na, na)
     g.profile(True)
     acc_g, _ = g.pass_(grid_s, s, 0, 2)
-    assert g.profile()["main_kernels"] == 16  # the wide tile
+    assert g.profile()["main_kernels"] == bits
     pos_g = g.state()[0]
     g.close()
-    for lo in [(40, 120, 70), (166, 167, 165)]:
+    for lo in [(40, 120, 70), (na - 4, na - 3, na - 5)]:
         o = oracle_lib.Oracle.from_workload(w)
-        na, inv = o.grid(grid_s * o.rho_max())
-        assert tuple(int(x) for x in na) == (170, 170, 170)
-        cell = o.bin(na, inv)
-        mask, block = _cone(na, lo, 8, 9)
-        acc_o, _ = o.pass_(na, inv, s, 0, 2, mask=mask)
+        nao, inv = o.grid(grid_s * o.rho_max())
+        assert tuple(int(x) for x in nao) == (na, na, na)
+        cell = o.bin(nao, inv)
+        mask, block = _cone(nao, lo, 8, 9)
+        acc_o, _ = o.pass_(nao, inv, s, 0, 2, mask=mask)
         sel = block[cell]
         assert int(sel.sum()) > 500
         assert np.array_equal(acc_g[sel], acc_o[sel]), lo
         assert np.array_equal(pos_g[:, sel], o.soa()[:, sel]), lo
-        _say(f"wide tile block {lo}: {int(sel.sum())} particles, "
+        _say(f"{na}^3 block {lo}: {int(sel.sum())} particles, "
              f"{int(np.sum(acc_o[sel] == 0))} rejected, equal")
         del o
 

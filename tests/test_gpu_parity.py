@@ -189,12 +189,13 @@ def test_crowded_cells_bitexact(srm, oracle_lib, dim, n, seed, f, sigma):
     g.close()
 
 
-@pytest.mark.parametrize("sigma,seed,f,bits", [(None, 71, 0.35, 1 | 16), (0.05, 5, 0.25, 1 | 16 | 2)])
+@pytest.mark.parametrize("sigma,seed,f,bits", [(None, 71, 0.35, 1 | 32),
+                                               (0.05, 5, 0.25, 1 | 32 | 16 | 2)])
 def test_tile_variants_bitexact(srm, oracle_lib, sigma, seed, f, bits):
     """The grid's mean occupancy picks the migration kernel: the standard
-    LDS tile (bit 1), the wide tile (16) as the region load nears the
-    standard capacity, then one wavefront per cell (2).  Runs that pass
-    through them equal the oracle sweep by sweep."""
+    LDS tile (bit 1), then the middle (32) and the wide (16) regions as the
+    region load nears each capacity, then one wavefront per cell (2).  Runs
+    that pass through them equal the oracle sweep by sweep."""
     kw = {} if sigma is None else dict(polydisperse_sigma=sigma)
     w = _mk(3, 20000, seed, f, **kw)
     o, g, sweeps = _sweep_parity(srm, oracle_lib, w, 1000, every=4, profile=True)
