@@ -192,6 +192,7 @@ struct WaveOwn {
 
 struct WaveLds {
     WaveOwn own[kWaveOwn];
+    float4 own32[kWaveOwn];  // own particles rounded to FP32, for the near-list filter
     int32_t nn[kWaveOwn];
     int32_t near[kWaveOwn * kWaveNear];  // slot q >= 0, or -(k + 1) for own particle k
     int32_t id[kWaveOwn];
@@ -292,22 +293,49 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
         o.z = (DIM == 3) ? Z[beg + k] : 0.0;
         o.r = POLY ? a.s * a.buf.rho[beg + k] : a.s;
         L.own[k] = o;
+        L.own32[k] = make_float4((float)o.x, (float)o.y, (float)o.z, (float)o.r);
         L.nn[k] = 0;
         L.id[k] = a.buf.id[beg + k];
     }
     if (lane == 0) L.nfail = 0;
     __syncthreads();
-    // A. near lists
+    // A. near lists.  A list only has to contain every candidate that can
+    // meet a trial (the exact FP64 test decides later), so the filter runs
+    // in FP32 with a margin that covers rounding: positions in [0, L) are
+    // off by at most L 2^-24 each, so each difference by ~3 L 2^-24 after the
+    // image shift; 4e-7 Lmax absolute plus 1e-5 relative on the reach bounds
+    // that with room to spare.  Extra entries only cost time.
+    const float bx32 = (float)a.g.box[0], by32 = (float)a.g.box[1], bz32 = (float)a.g.box[2];
+    const float hx32 = 0.5f * bx32, hy32 = 0.5f * by32, hz32 = 0.5f * bz32;
+    float lmax32 = bx32 > by32 ? bx32 : by32;
+    if (DIM == 3) lmax32 = lmax32 > bz32 ? lmax32 : bz32;
+    const float tol32 = 4e-7f * lmax32;
+    auto near32 = [&](const float4 &o, float px, float py, float pz, float reach) {
+        float dx = o.x - px, dy = o.y - py;
+        if (dx > hx32) dx -= bx32;
+        if (dx < -hx32) dx += bx32;
+        if (dy > hy32) dy -= by32;
+        if (dy < -hy32) dy += by32;
+        float qq = dx * dx + dy * dy;
+        if (DIM == 3) {
+            float dz = o.z - pz;
+            if (dz > hz32) dz -= bz32;
+            if (dz < -hz32) dz += bz32;
+            qq = qq + dz * dz;
+        }
+        const float rr = reach * 1.00001f + tol32;
+        return qq <= rr * rr;
+    };
+    const float cm2 = (float)(2.0 * a.c_m), cm3 = (float)(3.0 * a.c_m);
 #pragma unroll
     for (int r = 0; r < Rows<DIM>::kRanges; ++r) {
         for (int32_t q = lo[r] + lane; q < hi[r]; q += 64) {
             if (q >= beg && q < end) continue;
-            const double qx = X[q], qy = Y[q], qz = (DIM == 3) ? Z[q] : 0.0;
-            const double Rq = POLY ? a.s * a.buf.rho[q] : a.s;
+            const float qx = (float)X[q], qy = (float)Y[q], qz = (DIM == 3) ? (float)Z[q] : 0.0f;
+            const float Rq = (float)(POLY ? a.s * a.buf.rho[q] : a.s);
             for (int32_t k = 0; k < cnt; ++k) {
-                const WaveOwn o = L.own[k];
-                const double reach = (o.r + Rq) + 2.0 * a.c_m;
-                if (wave_q<DIM>(a.g, o.x, o.y, o.z, qx, qy, qz) <= reach * reach) {
+                const float4 o = L.own32[k];
+                if (near32(o, qx, qy, qz, (o.w + Rq) + cm2)) {
                     const int32_t slot = atomicAdd(&L.nn[k], 1);
                     if (slot < kWaveNear) L.near[k * kWaveNear + slot] = q;
                 }
@@ -315,12 +343,11 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
         }
     }
     for (int32_t j = lane; j < cnt; j += 64) {
-        const WaveOwn b = L.own[j];
+        const float4 b = L.own32[j];
         for (int32_t k = 0; k < cnt; ++k) {
             if (k == j) continue;
-            const WaveOwn o = L.own[k];
-            const double reach = (o.r + b.r) + 3.0 * a.c_m;
-            if (wave_q<DIM>(a.g, o.x, o.y, o.z, b.x, b.y, b.z) <= reach * reach) {
+            const float4 o = L.own32[k];
+            if (near32(o, b.x, b.y, b.z, (o.w + b.w) + cm3)) {
                 const int32_t slot = atomicAdd(&L.nn[k], 1);
                 if (slot < kWaveNear) L.near[k * kWaveNear + slot] = -(j + 1);
             }
