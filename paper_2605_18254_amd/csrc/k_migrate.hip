@@ -755,6 +755,7 @@ struct PlateOwn {
 template <int NEAR>
 struct PlateLds {
     PlateOwn own[kPlateOwn];
+    float4 own32[kPlateOwn];  // centre and radius rounded to FP32, for the near-list filter
     int32_t nn[kPlateOwn];
     int32_t near[kPlateOwn * NEAR];  // slot q >= 0, or -(k + 1) for own particle k
     int32_t nfail;
@@ -898,24 +899,42 @@ __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, Colour
         o.id = a.buf.id[q];
         o.pad = 0;
         S.own[k] = o;
+        S.own32[k] = make_float4((float)o.x, (float)o.y, (float)o.z, (float)o.a);
         S.nn[k] = 0;
     }
     if (lane == 0) S.nfail = 0;
     __syncthreads();
-    // A. near lists on centre distance
+    // A. near lists on centre distance.  A list only has to contain every
+    // disk that can meet a trial (the exact FP64 disk test decides later), so
+    // the filter runs in FP32 with a margin covering rounding (positions off
+    // by at most L 2^-24 each): 4e-7 Lmax absolute plus 1e-5 relative.
+    const float bx32 = (float)a.g.box[0], by32 = (float)a.g.box[1], bz32 = (float)a.g.box[2];
+    const float hx32 = 0.5f * bx32, hy32 = 0.5f * by32, hz32 = 0.5f * bz32;
+    float lmax32 = bx32 > by32 ? bx32 : by32;
+    lmax32 = lmax32 > bz32 ? lmax32 : bz32;
+    const float tol32 = 4e-7f * lmax32;
+    auto near32 = [&](const float4 &o, float px, float py, float pz, float reach) {
+        float dx = o.x - px, dy = o.y - py, dz = o.z - pz;
+        if (dx > hx32) dx -= bx32;
+        if (dx < -hx32) dx += bx32;
+        if (dy > hy32) dy -= by32;
+        if (dy < -hy32) dy += by32;
+        if (dz > hz32) dz -= bz32;
+        if (dz < -hz32) dz += bz32;
+        const float rr = reach * 1.00001f + tol32;
+        return (dx * dx + dy * dy) + dz * dz <= rr * rr;
+    };
+    const float cm2 = (float)(2.0 * a.c_m), cm3 = (float)(3.0 * a.c_m);
 #pragma unroll
     for (int r = 0; r < Rows<3>::kRanges; ++r) {
         for (int32_t q = lo[r] + lane; q < hi[r]; q += 64) {
             if (q >= beg && q < end) continue;
-            const double qx = a.buf.x[0][q], qy = a.buf.x[1][q], qz = a.buf.x[2][q];
-            const double aq = a.buf.rho ? a.s * a.buf.rho[q] : a.s;
+            const float qx = (float)a.buf.x[0][q], qy = (float)a.buf.x[1][q];
+            const float qz = (float)a.buf.x[2][q];
+            const float aq = (float)(a.buf.rho ? a.s * a.buf.rho[q] : a.s);
             for (int32_t k = 0; k < cnt; ++k) {
-                const PlateOwn o = S.own[k];
-                const double reach = (o.a + aq) + 2.0 * a.c_m;
-                const double dx = min_image(o.x - qx, a.g.box[0], a.g.half[0]);
-                const double dy = min_image(o.y - qy, a.g.box[1], a.g.half[1]);
-                const double dz = min_image(o.z - qz, a.g.box[2], a.g.half[2]);
-                if ((dx * dx + dy * dy) + dz * dz <= reach * reach) {
+                const float4 o = S.own32[k];
+                if (near32(o, qx, qy, qz, (o.w + aq) + cm2)) {
                     const int32_t slot = atomicAdd(&S.nn[k], 1);
                     if (slot < NEAR) S.near[k * NEAR + slot] = q;
                 }
@@ -923,15 +942,11 @@ __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, Colour
         }
     }
     for (int32_t j = lane; j < cnt; j += 64) {
-        const PlateOwn b = S.own[j];
+        const float4 b = S.own32[j];
         for (int32_t k = 0; k < cnt; ++k) {
             if (k == j) continue;
-            const PlateOwn o = S.own[k];
-            const double reach = (o.a + b.a) + 3.0 * a.c_m;
-            const double dx = min_image(o.x - b.x, a.g.box[0], a.g.half[0]);
-            const double dy = min_image(o.y - b.y, a.g.box[1], a.g.half[1]);
-            const double dz = min_image(o.z - b.z, a.g.box[2], a.g.half[2]);
-            if ((dx * dx + dy * dy) + dz * dz <= reach * reach) {
+            const float4 o = S.own32[k];
+            if (near32(o, b.x, b.y, b.z, (o.w + b.w) + cm3)) {
                 const int32_t slot = atomicAdd(&S.nn[k], 1);
                 if (slot < NEAR) S.near[k * NEAR + slot] = -(j + 1);
             }
