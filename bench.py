@@ -446,8 +446,8 @@ def grad_extra(steps, steer_steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is a design note only)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
 
