@@ -249,7 +249,7 @@ srm_status srm_rsa(int32_t dim, int32_t shape, int64_t n, const double *box, dou
 
 /* A workspace for configurations of n particles in a fixed periodic box.
  * Descriptor (steering clustered configurations toward a target radial
- * distribution; SRM's exact test stays the judge of admissibility):
+ * distribution; SRM's exact test still decides admissibility):
  *   g_b = norm_b * sum_{i<j} K_b(r_ij) w(r_ij),  b < nbins,
  *   K_b(r) = exp(-(r - c_b)^2 / (2 h^2)) / (h sqrt(2 pi)),
  *   c_b = (b + 1/2) D, h = D = r_c / nbins,
