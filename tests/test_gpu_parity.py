@@ -581,3 +581,32 @@ def test_batch_launch_shape_invariance_and_notconv(srm):
     for other in res[1:]:
         for a_, b_ in zip(res[0], other):
             assert np.array_equal(a_, b_)
+
+
+@pytest.mark.parametrize("dim,n,f,theory", [(3, 100_000, 0.30, (1 - 0.15) / 0.7 ** 3),
+                                            (2, 100_000, 0.35, (1 - 7 * 0.35 / 16) / 0.65 ** 2)])
+def test_equilibrium_contact_value_at_scale(srm, dim, n, f, theory):
+    """Single-trial passes without swelling sample the hard-particle
+    equilibrium (Metropolis with symmetric fixed-length moves).  The
+    SRM-grown start carries excess near-contacts (g(sigma+) ~2.2 in 2D) that
+    relax within ~1500 sweeps; after 1600, the contact value from srm_rdf at
+    N = 1e5 matches Carnahan-Starling (3D) or Henderson (2D) within 1.5%."""
+    w = _mk(dim, n, 23, f)
+    g = srm.SRM.from_workload(w, device=True)
+    assert g.run(5000)[0] == 0
+    pos, _, s, t = g.state()
+    g.close()
+    R = w.s_target
+    mc = srm.SRM.from_workload(w, pos=pos, s0=R, sweep0=t, n_l=1, c_w=0.0, c_m=0.25 * R)
+    nbins, r_max = 130, 2.6 * R  # bins of 0.02 R; contact at bin 100
+    acc = np.zeros(nbins)
+    for sweep in range(2400):
+        mc.sweep()
+        if sweep >= 1600 and sweep % 5 == 0:
+            acc += mc.rdf(nbins, r_max)[1]
+    mc.close()
+    gr = acc[100:106] / len(range(1600, 2400, 5))
+    width = r_max / nbins
+    b, a = np.polyfit((np.arange(6) + 0.5) * width, gr, 1)
+    _say(f"equilibrium {dim}D f={f}: g(sigma+) {a:.4f}, theory {theory:.4f}")
+    assert abs(a - theory) < 0.015 * theory, (a, theory, gr)
