@@ -85,3 +85,36 @@ def test_translation_and_permutation_invariance(oracle_lib):
     assert np.allclose(g0, g1, rtol=1e-12, atol=1e-12)
     assert np.allclose(g0, g2, rtol=1e-12, atol=1e-12)
     assert e0 == e1 == e2 == 0.0
+
+
+def test_thomas_process_matches_its_pair_correlation(oracle_lib):
+    """Points of a Thomas cluster process (Poisson parents, Poisson
+    offspring displaced by N(0, sigma^2) per axis, periodic unit box).
+    Given the realised cluster sizes m_c, a pair lies in one cluster with
+    probability W = sum m_c (m_c - 1) / (N (N - 1)), its separation then
+    having density exp(-r^2/(4 sigma^2)) / (4 pi sigma^2)^(3/2) (the
+    difference of two offspring offsets), and otherwise is uniform; so the
+    estimator's expectation is 1 - W + W exp(...) / (4 pi sigma^2)^(3/2)
+    (the intensity form 1 + exp(...) / (lambda_p (4 pi sigma^2)^(3/2)) on
+    average).  The soft estimator follows it from g ~ 14 near the origin
+    down to ~2, to the smoothing of a kernel much narrower than sigma."""
+    rng = np.random.default_rng(12)
+    lam_p, mu, sigma = 200.0, 20.0, 0.02
+    parents = rng.random((rng.poisson(lam_p), 3))
+    pts = [p + rng.normal(0.0, sigma, (rng.poisson(mu), 3)) for p in parents]
+    m = np.array([len(q) for q in pts], dtype=np.float64)
+    pos = np.ascontiguousarray((np.concatenate(pts) % 1.0).T)
+    n = pos.shape[1]
+    rc, nbins = 0.1, 32
+    g, e = oracle_lib.softrdf_forward(pos, np.zeros(n), dim=3, nbins=nbins, r_c=rc)
+    w_in = float(np.sum(m * (m - 1.0))) / (n * (n - 1.0))
+    c = (np.arange(nbins) + 0.5) * rc / nbins
+    dens = np.exp(-c * c / (4 * sigma * sigma)) / (4 * math.pi * sigma * sigma) ** 1.5
+    want = 1.0 - w_in + w_in * dens
+    # beyond ~3 sigma the cross-cluster pairs dominate, and with only ~200
+    # parents their count in a shell carries ~10% Poisson noise: compare the
+    # bins up to r = 0.06, where g falls from ~14 to ~2
+    ratio = g[3:20] / want[3:20]
+    assert np.all(np.abs(ratio - 1.0) < 0.06), np.round(ratio, 3)
+    assert abs(np.mean(ratio) - 1.0) < 0.03, np.round(ratio, 3)
+    assert want[3] > 12.0 and want[19] < 2.5  # the range the test spans
