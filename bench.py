@@ -24,8 +24,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Vector ALU issue rate of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz.
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Vector instruction issue of MI355X: a wavefront's VALU instruction holds
+# one 16-lane SIMD for 4 cycles; 256 CUs x 4 SIMDs at 2.4 GHz.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wavefront instructions per second
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 # Algorithmic HBM bytes per particle update of the migration kernel (3D
 # spheres, FP64 SoA, int32 ids): read the particle's position and id, write
 # its new position.
@@ -47,6 +49,7 @@ KERNEL_SOURCES = ["paper_2605_18254_amd/csrc/k_migrate.hip",
                   "paper_2605_18254_amd/csrc/srm_device.hpp",
                   "paper_2605_18254_amd/csrc/srm_internal.hpp"]
 TRAFFIC_FILE = "profiles/migrate_tile_spheres3d_n1e7.md"
+VALU_FILE = "profiles/migrate_tile_valu_spheres3d_n1e7.md"
 
 
 def kernel_sources_sha256():
@@ -58,11 +61,10 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def recorded_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when the
-    summary is missing, covers another kernel, or the sources changed."""
-    path = os.path.join(ROOT, TRAFFIC_FILE)
+def _record(relpath, kernel):
+    """The "- key: value" lines of a committed counter summary, or None when
+    it is missing, covers another kernel, or the kernel sources changed."""
+    path = os.path.join(ROOT, relpath)
     if not os.path.exists(path):
         return None
     rec = {}
@@ -71,11 +73,45 @@ def recorded_traffic(kernel):
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].strip().split(": ", 1)
                 rec[k.strip("`")] = v.strip().strip("`")
+    if rec.get("kernel") != kernel or rec.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return rec
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None."""
+    rec = _record(TRAFFIC_FILE, kernel)
     try:
-        if rec.get("kernel") != kernel or rec.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None if rec is None else {
+            "bytes_per_launch": float(rec["fetch_bytes_per_launch"]) +
+            float(rec["write_bytes_per_launch"]), "source": TRAFFIC_FILE}
+    except (KeyError, ValueError):
+        return None
+
+
+def recorded_valu(kernel, launch_s):
+    """The vector-ALU side of `kernel`: wavefront instruction counts per
+    launch from the committed counter summary over the live launch time.
+    Issued instructions include address, loop and random-number work, so
+    this is a ceiling on issue, not algorithmic flops; FP64 lane operations
+    count all 64 lanes of each instruction (an upper bound on useful ones)."""
+    rec = _record(VALU_FILE, kernel)
+    try:
+        if rec is None:
             return None
-        return {"bytes_per_launch": float(rec["fetch_bytes_per_launch"]) +
-                float(rec["write_bytes_per_launch"]), "source": TRAFFIC_FILE}
+        valu = float(rec["sq_insts_valu_per_launch"])
+        fp64 = {k: float(rec[f"sq_insts_valu_{k}_f64_per_launch"])
+                for k in ("add", "mul", "fma", "trans")}
+        lane_ops = 64.0 * (fp64["add"] + fp64["mul"] + fp64["trans"] + 2.0 * fp64["fma"])
+        return {"insts_per_launch": valu, "issue_rate": valu / launch_s,
+                "issue_peak": VALU_ISSUE_PEAK, "issue_frac": valu / launch_s / VALU_ISSUE_PEAK,
+                "fp64_insts_per_launch": sum(fp64.values()),
+                "fp64_lane_tflops_upper": lane_ops / launch_s / 1e12,
+                "fp64_peak_tflops": FP64_VECTOR_PEAK_TFLOPS,
+                "lds_insts_per_launch": float(rec["sq_insts_lds_per_launch"]),
+                "vmem_rd_insts_per_launch": float(rec["sq_insts_vmem_rd_per_launch"]),
+                "source": VALU_FILE}
     except (KeyError, ValueError):
         return None
 
@@ -99,6 +135,31 @@ def parse():
                     help="copy this many MiB device to device before the sweeps (a plain copy "
                          "kernel of known size, to calibrate HBM byte counters)")
     return ap.parse_args()
+
+
+def host_boundary(srm, w, torch):
+    """The boundary with host buffers, outside the timed region: srm_init
+    from host positions (the library copies them to the device), and
+    srm_get_state back to host memory; srm_init from positions already in
+    device memory beside it."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = srm.SRM.from_workload(w)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.state()
+    t2 = time.perf_counter()
+    g.close()
+    pos_d = torch.from_numpy(w.pos).cuda()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    g = srm.SRM.from_workload(w, pos=pos_d)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    g.close()
+    del pos_d
+    return {"init_from_host_s": t1 - t0, "state_to_host_s": t2 - t1,
+            "init_from_device_s": t4 - t3, "position_bytes_each_way": int(w.pos.nbytes)}
 
 
 def cpu_baseline(w, frac):
@@ -495,6 +556,7 @@ def main():
         g.sweep()
     trials = g.profile()["trials"]
     g.close()
+    boundary = host_boundary(srm, w, torch)
 
     updates = w.n * passes
     value = updates / dt
@@ -538,6 +600,7 @@ def main():
                      "phase_floor_bytes_per_launch": floor_per_launch,
                      "phase_floor_gbs": floor_per_launch / avg_launch_s / 1e9,
                      "traffic_source": traffic["source"] if traffic else None},
+        "valu": recorded_valu(main_name, avg_launch_s),
         "trial_moves_per_s": trials / dt,
         "trials_per_update": trials / max(updates, 1),
         "kernel_ms": {"bin": prof["ms_bin"], "migrate": mig_ms, "check": prof["ms_check"],
@@ -546,6 +609,9 @@ def main():
                       "achieved_gbs": (phase_bytes + BIN_BYTES * w.n * passes) / dt / 1e9,
                       "frac": (phase_bytes + BIN_BYTES * w.n * passes) / dt / 1e9 / HBM_PEAK_GBS},
     }
+    boundary["value_pcie_inclusive"] = updates / (dt + boundary["init_from_host_s"] +
+                                                  boundary["state_to_host_s"])
+    out["host_boundary"] = boundary
     if not args.no_extras:
         runs = {"n_scaling": n_scaling_extra,
                 "platelets": lambda: platelet_extra(3000),
