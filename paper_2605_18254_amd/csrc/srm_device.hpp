@@ -29,6 +29,9 @@ struct Grid {
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the
 // 4-word multiply/xor bijection with a Weyl-sequence key schedule.  The key
 // schedule is the same for every lane, so it stays in scalar registers.
+// Each round's two 32x32 -> 64-bit products are written as 64-bit
+// multiplies of zero-extended words, which gfx950 issues as one
+// v_mad_u64_u32 each instead of a v_mul_lo_u32 / v_mul_hi_u32 pair.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void philox4x32_10(uint32_t &x0, uint32_t &x1, uint32_t &x2,
                                               uint32_t &x3, uint32_t k0, uint32_t k1)
@@ -37,14 +40,14 @@ __device__ __forceinline__ void philox4x32_10(uint32_t &x0, uint32_t &x1, uint32
     constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = M0 * x0, hi0 = __umulhi(M0, x0);
-        const uint32_t lo1 = M1 * x2, hi1 = __umulhi(M1, x2);
-        const uint32_t y0 = hi1 ^ x1 ^ k0;
-        const uint32_t y2 = hi0 ^ x3 ^ k1;
+        const uint64_t p0 = (uint64_t)M0 * (uint64_t)x0;
+        const uint64_t p1 = (uint64_t)M1 * (uint64_t)x2;
+        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
         x0 = y0;
-        x1 = lo1;
+        x1 = (uint32_t)p1;
         x2 = y2;
-        x3 = lo0;
+        x3 = (uint32_t)p0;
         k0 += W0;
         k1 += W1;
     }
