@@ -50,6 +50,7 @@ KERNEL_SOURCES = ["paper_2605_18254_amd/csrc/k_migrate.hip",
                   "paper_2605_18254_amd/csrc/srm_internal.hpp"]
 TRAFFIC_FILE = "profiles/migrate_tile_spheres3d_n1e7.md"
 VALU_FILE = "profiles/migrate_tile_valu_spheres3d_n1e7.md"
+PLATELET_VALU_FILE = "profiles/migrate_platelet_valu_n2e5.md"
 
 
 def kernel_sources_sha256():
@@ -90,6 +91,20 @@ def recorded_traffic(kernel):
         return None
 
 
+def _valu_figures(rec, launch_s):
+    valu = float(rec["sq_insts_valu_per_launch"])
+    fp64 = {k: float(rec[f"sq_insts_valu_{k}_f64_per_launch"]) for k in ("add", "mul", "fma", "trans")}
+    lane_ops = 64.0 * (fp64["add"] + fp64["mul"] + fp64["trans"] + 2.0 * fp64["fma"])
+    return {"insts_per_launch": valu, "issue_rate": valu / launch_s,
+            "issue_peak": VALU_ISSUE_PEAK, "issue_frac": valu / launch_s / VALU_ISSUE_PEAK,
+            "fp64_insts_per_launch": sum(fp64.values()),
+            "fp64_lane_tflops_upper": lane_ops / launch_s / 1e12,
+            "fp64_peak_tflops": FP64_VECTOR_PEAK_TFLOPS,
+            "fp64_frac_upper": lane_ops / launch_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+            "lds_insts_per_launch": float(rec["sq_insts_lds_per_launch"]),
+            "vmem_rd_insts_per_launch": float(rec["sq_insts_vmem_rd_per_launch"])}
+
+
 def recorded_valu(kernel, launch_s):
     """The vector-ALU side of `kernel`: wavefront instruction counts per
     launch from the committed counter summary over the live launch time.
@@ -98,20 +113,19 @@ def recorded_valu(kernel, launch_s):
     count all 64 lanes of each instruction (an upper bound on useful ones)."""
     rec = _record(VALU_FILE, kernel)
     try:
-        if rec is None:
-            return None
-        valu = float(rec["sq_insts_valu_per_launch"])
-        fp64 = {k: float(rec[f"sq_insts_valu_{k}_f64_per_launch"])
-                for k in ("add", "mul", "fma", "trans")}
-        lane_ops = 64.0 * (fp64["add"] + fp64["mul"] + fp64["trans"] + 2.0 * fp64["fma"])
-        return {"insts_per_launch": valu, "issue_rate": valu / launch_s,
-                "issue_peak": VALU_ISSUE_PEAK, "issue_frac": valu / launch_s / VALU_ISSUE_PEAK,
-                "fp64_insts_per_launch": sum(fp64.values()),
-                "fp64_lane_tflops_upper": lane_ops / launch_s / 1e12,
-                "fp64_peak_tflops": FP64_VECTOR_PEAK_TFLOPS,
-                "lds_insts_per_launch": float(rec["sq_insts_lds_per_launch"]),
-                "vmem_rd_insts_per_launch": float(rec["sq_insts_vmem_rd_per_launch"]),
-                "source": VALU_FILE}
+        return None if rec is None else dict(_valu_figures(rec, launch_s), source=VALU_FILE)
+    except (KeyError, ValueError):
+        return None
+
+
+def recorded_platelet_valu(launch_s):
+    """The same figures for the platelet kernel (one wavefront per cell, both
+    near-list sizes together) on the N = 2e5 platelet runs, the FP64 side
+    against the vector FP64 peak."""
+    rec = _record(PLATELET_VALU_FILE, "k_migrate_platelet_wave")
+    try:
+        return None if rec is None else dict(_valu_figures(rec, launch_s),
+                                             source=PLATELET_VALU_FILE)
     except (KeyError, ValueError):
         return None
 
@@ -265,6 +279,7 @@ def platelet_extra(max_sweeps):
     import srm_inputs
 
     out = {}
+    plate_launches, plate_ms, plate_kinds = 0, 0.0, 0
     for tag, cap in (("isotropic", None), ("cap15", 15.0)):
         w = srm_inputs.make("platelets", cap_deg=cap)
         g = srm.SRM.from_workload(w, device=True)
@@ -284,6 +299,16 @@ def platelet_extra(max_sweeps):
         gap_c = g.critical_gap(0.0, hi, 30) if g.percolation(hi) else None
         dt_perc = time.perf_counter() - t1
         g.close()
+        # the same run again with the device-time profile on: the platelet
+        # kernel's launches and time (kept out of the timed run above)
+        g = srm.SRM.from_workload(w, device=True)
+        g.profile(enable=True)
+        g.run(max_sweeps)
+        prof = g.profile()
+        g.close()
+        plate_launches += prof["launches_migrate"]
+        plate_ms += prof["ms_migrate_main"]
+        plate_kinds |= prof["main_kernels"]
         out[tag] = {"converged": st == 0, "sweeps": info["sweeps"], "passes": info["passes"],
                     "s": dt, "updates_per_s": info["updates"] / dt,
                     "fraction": info["fraction"], "overlapping_pairs": overlaps,
@@ -293,6 +318,11 @@ def platelet_extra(max_sweeps):
         _say(f"platelets {tag}: {out[tag]}")
     out["workload"] = ("platelets N=2e5, thickness D/100, f_target=0.02, seed 2, c_w=0.01, "
                        "c_m=0.1*s_target, c_n=c_m/a_t, N_k=N_l=8")
+    launch_s = plate_ms / 1e3 / max(plate_launches, 1)
+    out["kernel"] = {"main_kernels": plate_kinds, "launches": plate_launches,
+                     "avg_launch_ms": launch_s * 1e3,
+                     # the platelet kernel (one wavefront per cell) ran alone
+                     "valu": recorded_platelet_valu(launch_s) if plate_kinds == 8 | 2 else None}
     return out
 
 def n_scaling_extra(sizes=(1_000, 10_000, 100_000, 1_000_000, 10_000_000)):
