@@ -289,3 +289,34 @@ def test_percolation_matches_a_doubled_box(oracle_lib, dim):
         assert got == ref, (gap, got, ref)
         seen.add(got)
     assert 0 in seen and (2 ** dim - 1) in seen   # both regimes covered
+
+
+@pytest.mark.parametrize("dim,axes,eta_ref", [
+    (2, 1, 1.12808737),   # disks (Mertens and Moore 2012)
+    (3, 7, 0.3418174),    # spheres (Lorenz and Ziff 2001)
+])
+def test_soft_shells_of_points_percolate_at_the_continuum_threshold(oracle_lib, dim, axes, eta_ref):
+    """With vanishing hard cores the soft shells are fully penetrable disks
+    (spheres) of radius gap/2 around Poisson points, whose wrapping threshold
+    is the continuum percolation threshold: reduced density
+    eta = N pi r^2 (N 4/3 pi r^3) of 1.128 in 2D and 0.342 in 3D.  Bisection
+    on the gap over 12 boxes of 2000 points lands within 6% (the mean sits
+    ~1.7% above, two standard errors of the sampling; wrapping along x in 2D,
+    along any axis in 3D, whose finite-size shifts are small)."""
+    import math
+    etas = []
+    for seed in range(12):
+        rng = np.random.default_rng(seed)
+        n = 2000
+        o = _balls(oracle_lib, rng.random((dim, n)), 1e-9)
+        lo, hi = 0.0, (0.1 if dim == 2 else 0.3)
+        assert not (o.percolation(lo) & axes) and (o.percolation(hi) & axes)
+        for _ in range(24):
+            mid = 0.5 * (lo + hi)
+            if o.percolation(mid) & axes:
+                hi = mid
+            else:
+                lo = mid
+        r = 0.5 * (hi + 2e-9)
+        etas.append(n * (math.pi * r * r if dim == 2 else 4.0 / 3.0 * math.pi * r ** 3))
+    assert abs(np.mean(etas) / eta_ref - 1.0) < 0.06, (np.mean(etas), etas)
