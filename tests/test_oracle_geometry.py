@@ -320,3 +320,28 @@ def test_soft_shells_of_points_percolate_at_the_continuum_threshold(oracle_lib, 
         r = 0.5 * (hi + 2e-9)
         etas.append(n * (math.pi * r * r if dim == 2 else 4.0 / 3.0 * math.pi * r ** 3))
     assert abs(np.mean(etas) / eta_ref - 1.0) < 0.06, (np.mean(etas), etas)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nearest_distances_of_poisson_points_follow_hertz(oracle_lib, dim):
+    """Uniform points in the periodic unit box: the distance from a point to
+    its nearest neighbour exceeds r with probability (1 - V(r))^(N-1), V the
+    disk (ball) area (volume) of radius r (Hertz's distribution, exact in a
+    periodic box for r below half the edge).  The empirical distribution of
+    the oracle's nearest distances stays within 0.04 of it in the sup norm,
+    and its mean within 3% of the distribution's."""
+    import math
+    n = 3000
+    rng = np.random.default_rng(40 + dim)
+    o = _balls(oracle_lib, rng.random((dim, n)), 1e-9)
+    d = np.sort(o.nearest_brute(0.45))
+    assert np.all(np.isfinite(d))
+    vol = (lambda r: math.pi * r * r) if dim == 2 else (lambda r: 4.0 / 3.0 * math.pi * r ** 3)
+    cdf = np.array([1.0 - (1.0 - vol(r)) ** (n - 1) for r in d])
+    emp_hi = np.arange(1, n + 1) / n
+    emp_lo = np.arange(0, n) / n
+    assert max(np.max(np.abs(emp_hi - cdf)), np.max(np.abs(emp_lo - cdf))) < 0.04
+    rs = np.linspace(0.0, 0.45, 200001)
+    surv = (1.0 - np.array([vol(r) for r in rs])) ** (n - 1)
+    mean = float(np.sum(0.5 * (surv[1:] + surv[:-1])) * (rs[1] - rs[0]))
+    assert abs(d.mean() / mean - 1.0) < 0.03, (d.mean(), mean)
