@@ -345,3 +345,25 @@ def test_nearest_distances_of_poisson_points_follow_hertz(oracle_lib, dim):
     surv = (1.0 - np.array([vol(r) for r in rs])) ** (n - 1)
     mean = float(np.sum(0.5 * (surv[1:] + surv[:-1])) * (rs[1] - rs[0]))
     assert abs(d.mean() / mean - 1.0) < 0.03, (d.mean(), mean)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_distance_histogram_of_poisson_points(oracle_lib, dim):
+    """Uniform points in the periodic unit box: the expected number of pairs
+    in the distance bin [r_b, r_b+1) is N (N - 1) / 2 times the shell area
+    (volume) for r below half the edge; every bin of the oracle's histogram
+    lies within 5 standard deviations of it (pair counts ~ Poisson here)."""
+    import math
+    n, nbins, r_max = 3000, 40, 0.2
+    rng = np.random.default_rng(60 + dim)
+    o = _balls(oracle_lib, rng.random((dim, n)), 1e-9)
+    got = o.rdf_brute(nbins, r_max).astype(np.float64)
+    edges = np.arange(nbins + 1) * (r_max / nbins)
+    if dim == 2:
+        shell = math.pi * (edges[1:] ** 2 - edges[:-1] ** 2)
+    else:
+        shell = 4.0 / 3.0 * math.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
+    expect = 0.5 * n * (n - 1) * shell
+    z = (got - expect) / np.sqrt(expect)
+    assert np.all(np.abs(z[2:]) < 5.0), z
+    assert abs(got.sum() / expect.sum() - 1.0) < 0.01
