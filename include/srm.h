@@ -109,7 +109,8 @@ srm_status srm_init(const srm_params *p, const double *pos, const double *rho,
  * move every particle (Algorithm 3 over the 2^dim-colour cell schedule) and
  * check for overlaps (Algorithm 6); on the first clean pass commit s'; else
  * discard the swollen copy and shake the committed state (n_k passes at its
- * own radii).  info may be NULL. */
+ * own radii).  info may be NULL.  Allocates no device memory: every buffer
+ * it uses was allocated by srm_init. */
 srm_status srm_sweep(srm_ctx *ctx, srm_sweep_info *info);
 
 /* Repeat srm_sweep until the committed scale equals s_target (Sec. 2 step
