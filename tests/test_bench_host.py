@@ -42,3 +42,12 @@ def test_valu_figures_arithmetic():
     assert f["fp64_insts_per_launch"] == 65
     # FMA counts two operations, every instruction all 64 lanes
     assert f["fp64_lane_tflops_upper"] == pytest.approx(64 * (10 + 20 + 5 + 60) / 1e-6 / 1e12)
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(bench.ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and not r.stdout.strip()
