@@ -3,8 +3,8 @@
  * Migration (SRM) sweep.  TEST INFRASTRUCTURE ONLY: it is the reference the
  * GPU library is checked against and is never called by the library.
  *
- * It follows the paper's Algorithms 1-6 (Section 2) step by step, with the
- * readings listed below.  Positions are stored in particle-id order,
+ * It computes what the paper's Algorithms 1-6 (Section 2) define, one
+ * particle at a time in a sequential order, with the readings listed below.  Positions are stored in particle-id order,
  * array-of-structures pos[3*i + a] (the paper's particle set P with
  * positions r_i); cell lists are Alg. 2's per-cell particle lists, filled in
  * ascending id.
@@ -28,9 +28,10 @@
  *    within a phase cells by ascending linear index c = cx + Nx*(cy + Ny*cz);
  *    within a cell ascending particle id.  Cells of one colour never share a
  *    3^d neighbourhood, so any order of them gives the same result.
- *  - collision test (Alg. 5): cell of the tested position, 3^d neighbour
- *    cells of the current lists, the particle itself excluded, minimum image
- *    per axis, squared form q <= (R_i + R_j)^2 (touching counts as overlap).
+ *  - collision test (Alg. 5): contact with any other particle in its current
+ *    state, minimum image per axis, squared form q <= (R_i + R_j)^2 (touching
+ *    counts as overlap); candidates come from the cells touching the cell of
+ *    the tested position.
  *  - unit random vector (Alg. 3): Philox4x32-10 counter-based draws keyed by
  *    the seed, counter (id, sweep, kind<<31 | k<<16 | l<<8 | call, stream);
  *    Marsaglia's rejection method for a uniform point on the sphere (3D) or
@@ -334,49 +335,68 @@ int o_bin(const o_params *p, const int64_t na[3], const double inv_w[3],
 }
 
 /* ------------------------------------------------------------------ */
-/* Alg. 5: collision check for particle i tested at position y.        */
+/* Alg. 5: does particle i, tested at position y, meet another particle?  */
 /* ------------------------------------------------------------------ */
+/* Contact of particle i at (y, normal ny) with particle j in its current
+ * state.  Balls: the minimum-image squared centre distance is at most
+ * (R_i + R_j)^2 (touching counts).  Thin disks: they intersect, tested with
+ * the lower particle id as disk 1 so that both orders of a pair agree. */
+static int o_contact(const o_state *st, int64_t i, const double y[3], const double ny[3],
+                     int64_t j, double s)
+{
+    const o_params *p = &st->p;
+    const double *xj = &st->pos[3 * j];
+    double Ri = o_radius(st, s, i), Rj = o_radius(st, s, j);
+    if (p->shape == O_PLATELET) {
+        const double *nj = &st->nrm[3 * j];
+        return (i < j) ? o_disks_intersect(y, ny, Ri, xj, nj, Rj, p->box)
+                       : o_disks_intersect(xj, nj, Rj, y, ny, Ri, p->box);
+    }
+    double d0 = o_minimg(y[0] - xj[0], p->box[0]);
+    double d1 = o_minimg(y[1] - xj[1], p->box[1]);
+    double q = d0 * d0 + d1 * d1;
+    if (p->dim == 3) {
+        double d2 = o_minimg(y[2] - xj[2], p->box[2]);
+        q = q + d2 * d2;
+    }
+    double sig = Ri + Rj;
+    return q <= sig * sig;
+}
+
+/* Linear indices of the cells that touch cell c (c itself included) under
+ * periodic wrap: one cell either side along every axis split into cells, a
+ * single cell along an axis that is not split. */
+static int o_touching_cells(const o_cells *g, const int64_t c[3], int64_t out[27])
+{
+    int count = 0;
+    int64_t span[3];
+    for (int a = 0; a < 3; ++a) span[a] = (g->na[a] > 1) ? 3 : 1;
+    for (int64_t k = 0; k < span[0] * span[1] * span[2]; ++k) {
+        int64_t off[3] = {k % span[0], (k / span[0]) % span[1], k / (span[0] * span[1])};
+        int64_t nc[3];
+        for (int a = 0; a < 3; ++a) {
+            int64_t shift = (span[a] == 3) ? off[a] - 1 : 0;
+            nc[a] = (c[a] + shift + g->na[a]) % g->na[a];
+        }
+        out[count++] = o_linear(g, nc);
+    }
+    return count;
+}
+
+/* Particle i at y collides when it is in contact with any other particle.
+ * Every particle close enough to touch lies in a cell touching y's cell (the
+ * cell edge covers the largest contact distance), so the lists of those
+ * cells hold every candidate. */
 static int o_collides(const o_state *st, const o_cells *g, int64_t i,
                       const double y[3], const double ny[3], double s)
 {
-    const o_params *p = &st->p;
-    int64_t c[3];
-    o_cell_coords(g, y, p->dim, c);
-    double Ri = o_radius(st, s, i);
-    int64_t lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-        if (g->na[a] >= 3) { lo[a] = -1; hi[a] = 1; }
-        else { lo[a] = 0; hi[a] = 0; }
-    }
-    for (int64_t sz = lo[2]; sz <= hi[2]; ++sz)
-    for (int64_t sy = lo[1]; sy <= hi[1]; ++sy)
-    for (int64_t sx = lo[0]; sx <= hi[0]; ++sx) {
-        int64_t nc[3];
-        nc[0] = (c[0] + sx + g->na[0]) % g->na[0];
-        nc[1] = (c[1] + sy + g->na[1]) % g->na[1];
-        nc[2] = (c[2] + sz + g->na[2]) % g->na[2];
-        int64_t cl = o_linear(g, nc);
-        for (int64_t m = g->start[cl]; m < g->start[cl + 1]; ++m) {
+    int64_t c[3], cells[27];
+    o_cell_coords(g, y, st->p.dim, c);
+    int count = o_touching_cells(g, c, cells);
+    for (int b = 0; b < count; ++b) {
+        for (int64_t m = g->start[cells[b]]; m < g->start[cells[b] + 1]; ++m) {
             int64_t j = g->member[m];
-            if (j == i) continue;
-            const double *xj = &st->pos[3 * j];
-            double Rj = o_radius(st, s, j);
-            if (p->shape == O_PLATELET) {
-                int hit = (i < j)
-                    ? o_disks_intersect(y, ny, Ri, xj, &st->nrm[3 * j], Rj, p->box)
-                    : o_disks_intersect(xj, &st->nrm[3 * j], Rj, y, ny, Ri, p->box);
-                if (hit) return 1;
-                continue;
-            }
-            double d0 = o_minimg(y[0] - xj[0], p->box[0]);
-            double d1 = o_minimg(y[1] - xj[1], p->box[1]);
-            double q = d0 * d0 + d1 * d1;
-            if (p->dim == 3) {
-                double d2 = o_minimg(y[2] - xj[2], p->box[2]);
-                q = q + d2 * d2;
-            }
-            double sig = Ri + Rj;
-            if (q <= sig * sig) return 1;
+            if (j != i && o_contact(st, i, y, ny, j, s)) return 1;
         }
     }
     return 0;

@@ -2,24 +2,28 @@
 
 Flags: -ffp-contract=off keeps every double expression as written (no fused
 multiply-add), which the bit-exact contract of the library depends on;
-packed FP32 instructions are disabled.
+packed FP32 instructions are disabled.  Each source compiles to its own
+object in parallel, then one link step makes the shared library.
 """
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
+OBJDIR = os.path.join(LIBDIR, "obj")
 LIB = os.path.join(LIBDIR, "libsrm.so")
-SOURCES = ["srm_api.hip", "k_bin.hip", "k_migrate.hip", "k_pairs.hip", "k_softrdf.hip", "srm_batch.hip", "k_diag.hip", "k_perc.hip", "srm_rsa.hip"]
+SOURCES = ["srm_api.hip", "k_bin.hip", "k_migrate.hip", "k_pairs.hip", "k_softrdf.hip",
+           "srm_batch.hip", "k_diag.hip", "k_perc.hip", "srm_rsa.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-ffp-contract=off", "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
@@ -30,22 +34,34 @@ def sources():
     return [os.path.join(CSRC, s) for s in SOURCES]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into _lib/libsrm.so; returns its path."""
-    os.makedirs(LIBDIR, exist_ok=True)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *sources(), "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libsrm.so")
+        raise RuntimeError("hipcc failed: " + " ".join(cmd[-3:]))
     if verbose and res.stderr.strip():
         # warnings (the host pass does not know the packed-fp32 feature)
         lines = [l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l]
         if lines:
             sys.stderr.write("\n".join(lines) + "\n")
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every HIP source into _lib/libsrm.so; returns its path."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    objs, cmds = [], []
+    for src in sources():
+        obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+        objs.append(obj)
+        cmds.append([HIPCC, *FLAGS, *inc, "-c", src, "-o", obj])
+    jobs = jobs or min(len(cmds), os.cpu_count() or 4, 16)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(lambda c: _run(c, verbose), cmds))
+    tmp = LIB + ".tmp%d" % os.getpid()
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

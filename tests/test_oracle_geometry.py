@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import srm_inputs
-from tests import brute
+from tests import brute, disk_ref
 
 
 def _state(oracle_lib, dim, n, seed, f):
@@ -106,28 +106,6 @@ def test_disks_perpendicular_analytic(oracle_lib):
                 assert got == expect, (h, y2)
 
 
-def _chords_overlap_ref(c1, n1, a1, c2, n2, a2):
-    """Independent formulation: solve for a point on the planes' common line
-    with a 3x3 linear system, then compare chord intervals with sqrt in
-    long double.  Returns (answer, margin)."""
-    d = (c2 - c1).astype(np.longdouble)
-    n1l, n2l = n1.astype(np.longdouble), n2.astype(np.longdouble)
-    u = np.cross(n1l, n2l)
-    M = np.array([n1, n2, np.cross(n1, n2)], dtype=np.float64)
-    rhs = np.array([0.0, float(np.dot(n2l, d)), 0.0])
-    p = np.linalg.solve(M, rhs).astype(np.longdouble)  # on both planes, closest to c1
-    uu = np.dot(u, u)
-    e1 = p
-    A = a1 * a1 - np.dot(e1, e1)
-    t1 = np.dot(d - p, u) / uu
-    e2 = d - (p + t1 * u)
-    B = a2 * a2 - np.dot(e2, e2)
-    if A < 0 or B < 0:
-        return False, float(min(abs(A), abs(B)))
-    reach = np.sqrt(A / uu) + np.sqrt(B / uu)
-    return bool(abs(t1) <= reach), float(abs(abs(t1) - reach))
-
-
 def test_disks_random_against_independent_formulation(oracle_lib):
     rng = np.random.default_rng(11)
     checked = hits = 0
@@ -140,7 +118,7 @@ def test_disks_random_against_independent_formulation(oracle_lib):
         if np.linalg.norm(c2 - c1) > a1 + a2:
             assert not got
             continue
-        ref, margin = _chords_overlap_ref(c1, n1, a1, c2, n2, a2)
+        ref, margin = disk_ref.chords_overlap_ref(c1, n1, a1, c2, n2, a2)
         if margin < 1e-9:
             continue
         assert got == ref

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from tests import rocrand_ref
-from tests.test_oracle_geometry import _chords_overlap_ref
+from tests.disk_ref import chords_overlap_ref as _chords_overlap_ref
 
 BALL, PLATELET = 0, 1
 

@@ -1,0 +1,27 @@
+"""The oracle built with gcc's address and undefined-behaviour sanitizers
+runs every entry point (sweeps to the target for disks, spheres and
+platelets, mono- and polydisperse, masked passes, global checks, pairs,
+percolation, distance histogram, nearest neighbours, soft g(r) and its
+gradient, RSA) without a report (CPU only)."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_oracle_under_asan_and_ubsan(tmp_path):
+    exe = tmp_path / "oracle_sanitize"
+    src = os.path.join(HERE, "helpers", "oracle_sanitize_main.c")
+    subprocess.check_call(["gcc", "-std=c11", "-O1", "-g", "-ffp-contract=off", "-fno-fast-math",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                           "-fno-omit-frame-pointer", src, "-o", str(exe), "-lm"])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    res = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=300)
+    assert res.returncode == 0, res.stdout + res.stderr
+    assert "runtime error" not in res.stderr and "AddressSanitizer" not in res.stderr, res.stderr
+    assert res.stdout.strip().endswith("ok")
