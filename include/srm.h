@@ -113,10 +113,20 @@ srm_status srm_init(const srm_params *p, const double *pos, const double *rho,
  * it uses was allocated by srm_init. */
 srm_status srm_sweep(srm_ctx *ctx, srm_sweep_info *info);
 
-/* Repeat srm_sweep until the committed scale equals s_target (Sec. 2 step
- * e).  SRM_ENOTCONV after max_sweeps sweeps; the committed state is then the
- * last admissible one.  info may be NULL. */
-srm_status srm_run_to_fraction(srm_ctx *ctx, int32_t max_sweeps, srm_run_info *info);
+/* Repeat srm_sweep until the committed volume fraction reaches f_target
+ * (Sec. 2 step e: stop at the target fraction).  In these sweeps swelling
+ * stops at the scale s_f whose fraction is f_target (to rounding:
+ * s_f = (f_target |box| / (w sum_i rho_i^dim))^(1/dim), w = pi for disks,
+ * 4 pi/3 for spheres, 2 pi thick_ratio for platelets), or at s_target when
+ * that is smaller; f_target <= 0 means s_target itself.  An intermediate
+ * target serves staged protocols (grow to f1, change the rates in a new
+ * context from the saved state, continue); srm_sweep outside this call
+ * always swells toward s_target.  The run ends when the committed scale
+ * equals the stop scale.  SRM_ENOTCONV after max_sweeps sweeps; the
+ * committed state is then the last admissible one.  SRM_EINVAL if f_target
+ * is NaN.  info may be NULL. */
+srm_status srm_run_to_fraction(srm_ctx *ctx, double f_target, int32_t max_sweeps,
+                               srm_run_info *info);
 
 /* Pairs i < j of the committed state (original ids) whose shapes come within
  * `gap` >= 0 of each other: balls with q_ij <= ((R_i + R_j) + gap)^2 under
@@ -124,8 +134,9 @@ srm_status srm_run_to_fraction(srm_ctx *ctx, int32_t max_sweeps, srm_run_info *i
  * studies, Sec. 3.3); platelets whose disks, with radii grown to a + gap/2,
  * intersect (gap = 0: the admissibility test itself).  Written to ij (host
  * or device per mem_kind) as (i, j) int32 pairs sorted by (i, j); *count =
- * number of pairs (fewer than 2^31).  SRM_ECAPACITY (nothing written) if
- * *count > cap. */
+ * number of pairs.  Needs 2 R_max + gap <= min(L_a)/2 (SRM_EINVAL
+ * otherwise).  SRM_ECAPACITY (nothing written, *count = the number of
+ * pairs) if *count > cap or *count > 2^31 - 1. */
 srm_status srm_pairs(srm_ctx *ctx, double gap, int64_t cap, int32_t *ij, int64_t *count,
                      int32_t mem_kind);
 

@@ -90,6 +90,8 @@ def lib():
         L.o_swell.argtypes = [C.POINTER(Params), C.c_double]
         L.o_swell.restype = C.c_double
         L.o_sweep.argtypes = [C.POINTER(State), C.POINTER(SweepInfo), C.POINTER(C.c_uint8)]
+        L.o_run_to.argtypes = [C.POINTER(State), C.c_double, C.c_int32, C.POINTER(C.c_int64),
+                               C.POINTER(C.c_int64)]
         L.o_run.argtypes = [C.POINTER(State), C.c_int32, C.POINTER(C.c_int64),
                             C.POINTER(C.c_int64)]
         L.o_pairs_brute.argtypes = [C.POINTER(State), C.c_double, C.c_double, C.c_int64,
@@ -110,7 +112,7 @@ def lib():
                             C.c_int64, dp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                             C.POINTER(C.c_int64)]
         L.o_rsa.restype = C.c_int
-        for f in ("o_pass", "o_overlap", "o_sweep", "o_run", "o_rdf_brute", "o_bin",
+        for f in ("o_pass", "o_overlap", "o_sweep", "o_run", "o_run_to", "o_rdf_brute", "o_bin",
                   "o_nearest_brute", "o_percolation"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -335,9 +337,12 @@ class Oracle:
                  n_failed_last=info.n_failed_last)
         return d, acc
 
-    def run(self, max_sweeps: int):
+    def run(self, max_sweeps: int, s_stop=None):
+        """Sweep until s == s_stop (default s_target), swelling clamped at
+        s_stop; returns (status, sweeps, passes)."""
         sw, ps = C.c_int64(0), C.c_int64(0)
-        rc = lib().o_run(C.byref(self.st), int(max_sweeps), C.byref(sw), C.byref(ps))
+        stop = self.params.s_target if s_stop is None else float(s_stop)
+        rc = lib().o_run_to(C.byref(self.st), stop, int(max_sweeps), C.byref(sw), C.byref(ps))
         return rc, sw.value, ps.value
 
     # -- analysis ------------------------------------------------------------

@@ -516,22 +516,28 @@ double o_rho_max(const o_state *st)
     return m;
 }
 
-/* Radius scale after one swelling step. */
-double o_swell(const o_params *p, double s)
+/* Radius scale after one swelling step, clamped at s_stop (the target
+ * scale, or an intermediate one of a staged run). */
+static double o_swell_to(const o_params *p, double s, double s_stop)
 {
     double ds = p->c_w * p->s_target;
     double s1 = s + ds;
-    return (s1 < p->s_target) ? s1 : p->s_target;
+    return (s1 < s_stop) ? s1 : s_stop;
+}
+
+double o_swell(const o_params *p, double s)
+{
+    return o_swell_to(p, s, p->s_target);
 }
 
 /* ------------------------------------------------------------------ */
 /* Alg. 1: one iteration of the main loop (one sweep).                 */
 /* ------------------------------------------------------------------ */
-int o_sweep(o_state *st, o_sweep_info *info, uint8_t *acc_last)
+static int o_sweep_to(o_state *st, double s_stop, o_sweep_info *info, uint8_t *acc_last)
 {
     const o_params *p = &st->p;
     int64_t n = p->n;
-    double s1 = o_swell(p, st->s);
+    double s1 = o_swell_to(p, st->s, s_stop);
     int64_t na[3]; double inv_w[3];
     o_grid(p, s1 * o_rho_max(st), na, inv_w);
     size_t bytes = sizeof(double) * 3 * (size_t)(n > 0 ? n : 1);
@@ -583,18 +589,26 @@ int o_sweep(o_state *st, o_sweep_info *info, uint8_t *acc_last)
     return O_OK;
 }
 
-/* Alg. 1 while loop: sweep until s == s_target or max_sweeps sweeps. */
-int o_run(o_state *st, int32_t max_sweeps, int64_t *sweeps_out, int64_t *passes_out)
+int o_sweep(o_state *st, o_sweep_info *info, uint8_t *acc_last)
+{
+    return o_sweep_to(st, st->p.s_target, info, acc_last);
+}
+
+/* Alg. 1 while loop: sweep until s == s_stop (swelling clamped there) or
+ * max_sweeps sweeps.  s_stop is the target scale, or a smaller one for a
+ * stage of a staged run. */
+int o_run_to(o_state *st, double s_stop, int32_t max_sweeps, int64_t *sweeps_out,
+             int64_t *passes_out)
 {
     int64_t sweeps = 0, passes = 0;
-    while (st->s < st->p.s_target) {
+    while (st->s < s_stop) {
         if (sweeps >= max_sweeps) {
             if (sweeps_out) *sweeps_out = sweeps;
             if (passes_out) *passes_out = passes;
             return O_ENOTCONV;
         }
         o_sweep_info info;
-        int rc = o_sweep(st, &info, NULL);
+        int rc = o_sweep_to(st, s_stop, &info, NULL);
         if (rc) return rc;
         sweeps++;
         passes += info.passes_main + info.passes_shake;
@@ -602,6 +616,11 @@ int o_run(o_state *st, int32_t max_sweeps, int64_t *sweeps_out, int64_t *passes_
     if (sweeps_out) *sweeps_out = sweeps;
     if (passes_out) *passes_out = passes;
     return O_OK;
+}
+
+int o_run(o_state *st, int32_t max_sweeps, int64_t *sweeps_out, int64_t *passes_out)
+{
+    return o_run_to(st, st->p.s_target, max_sweeps, sweeps_out, passes_out);
 }
 
 /* ------------------------------------------------------------------ */

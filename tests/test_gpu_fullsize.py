@@ -169,3 +169,33 @@ def test_fullsize_platelet_pass_matches_oracle(srm, oracle_lib, cap):
     assert np.array_equal(nrm_g, np.ascontiguousarray(o.nrm.T))
     _say(f"platelets cap={cap}: {int(np.sum(acc_o == 0))} rejected, "
          f"{int(np.sum(acc_o > 1))} on a later trial, equal")
+
+
+def test_fullsize_pair_count_beyond_int32_is_refused(srm, workload):
+    """10^7 uniform points with a gap of 0.0225 have about
+    N^2/2 * (4/3) pi gap^3 = 2.4e9 pairs, more than the int32 row offsets
+    hold: srm_pairs reports SRM_ECAPACITY with the exact 64-bit count before
+    any offset scan or emit kernel runs, and percolation refuses likewise.
+    A gap beyond half the box less the diameters is refused as invalid."""
+    import ctypes as C
+
+    w = workload
+    g = srm.SRM.from_workload(w, device=True)
+    cnt = C.c_int64(-1)
+    buf = np.zeros(8, dtype=np.int32)
+    _say("pairs at gap 0.0225 on 1e7 points")
+    st = srm.lib().srm_pairs(g._ctx, 0.0225, 4, C.c_void_p(buf.ctypes.data), C.byref(cnt), 0)
+    expect = 0.5 * w.n * (w.n - 1) * (4.0 / 3.0) * math.pi * 0.0225 ** 3
+    assert st == srm.ECAPACITY and cnt.value > 2**31 - 1
+    assert abs(cnt.value - expect) < 1e-3 * expect, (cnt.value, expect)
+    assert not buf.any()
+    m = C.c_int32(-1)
+    assert srm.lib().srm_percolation(g._ctx, 0.0225, C.byref(m)) == srm.ECAPACITY
+    st = srm.lib().srm_pairs(g._ctx, 0.6, 0, None, C.byref(cnt), 0)
+    assert st == srm.EINVAL
+    # a moderate gap still enumerates (counted only)
+    st = srm.lib().srm_pairs(g._ctx, 0.002, 0, None, C.byref(cnt), 0)
+    expect = 0.5 * w.n * (w.n - 1) * (4.0 / 3.0) * math.pi * 0.002 ** 3
+    assert st == srm.ECAPACITY and abs(cnt.value - expect) < 0.01 * expect
+    g.close()
+    _say(f"refused {cnt.value} pairs correctly")

@@ -328,6 +328,33 @@ def test_not_converged_keeps_admissible_state(srm, oracle_lib):
     g.close()
 
 
+@pytest.mark.parametrize("dim,n,f_mid", [(2, 1500, 0.3), (3, 3000, 0.2)])
+def test_staged_run_to_intermediate_fraction(srm, oracle_lib, dim, n, f_mid):
+    """srm_run_to_fraction with an intermediate target stops exactly at the
+    scale whose fraction is f_mid, bit-identical to the oracle run with the
+    same stop scale; the next call continues to the context's target, again
+    bit-identical; a target above the context's stops at s_target."""
+    w = _mk(dim, n, 97 + dim, 0.5 if dim == 2 else 0.35, c_w=0.03)
+    g = srm.SRM.from_workload(w)
+    st, info = g.run(2000, f_target=f_mid)
+    assert st == 0 and info["s"] < w.s_target
+    assert abs(info["fraction"] - f_mid) <= 4e-16 * 8
+    o = oracle_lib.Oracle.from_workload(w)
+    rc, sweeps, passes = o.run(2000, s_stop=info["s"])
+    assert rc == 0 and sweeps == info["sweeps"] and passes == info["passes"]
+    _assert_same_state(g, o, "at the intermediate target")
+    assert g.run(10, f_target=f_mid)[1]["sweeps"] == 0  # already there
+    st, info2 = g.run(2000, f_target=0.99)
+    rc, sweeps, passes = o.run(2000)
+    assert st == 0 and rc == 0 and info2["s"] == w.s_target
+    assert sweeps == info2["sweeps"] and passes == info2["passes"]
+    _assert_same_state(g, o, "at the final target")
+    import ctypes as C
+    ri = srm.RunInfo()
+    assert srm.lib().srm_run_to_fraction(g._ctx, float("nan"), 5, C.byref(ri)) == srm.EINVAL
+    g.close()
+
+
 def test_resume_is_bitexact(srm):
     w = _mk(3, 4000, 95, 0.3)
     a = srm.SRM.from_workload(w)

@@ -381,3 +381,18 @@ def test_polydisperse_run_admissible(oracle_lib):
     assert not brute.any_overlap(o.pos, radii, w.box, 3)
     f = 4.0 / 3.0 * math.pi * float(np.sum(radii ** 3))
     assert abs(f - 0.4) < 1e-14
+
+
+def test_staged_run_stops_at_the_given_scale(oracle_lib):
+    """A run with an intermediate stop scale ends exactly there with no
+    overlapping pair (all pairs), having swollen by c_w s_target per
+    committed sweep; continuing runs on to s_target."""
+    w = _mk(2, 600, 41, f=0.5)
+    o = oracle_lib.Oracle.from_workload(w, c_w=0.03)
+    stop = 0.62 * w.s_target
+    rc, sweeps, passes = o.run(2000, s_stop=stop)
+    assert rc == 0 and o.s == stop and sweeps >= math.ceil(0.62 / 0.03)
+    assert not brute.any_overlap(o.pos, np.full(o.n, o.s), w.box, 2)
+    rc, _, _ = o.run(2000)
+    assert rc == 0 and o.s == w.s_target
+    assert not brute.any_overlap(o.pos, np.full(o.n, o.s), w.box, 2)
