@@ -7,6 +7,15 @@ N_k = N_l = 8.  A step is one SRM sweep (Algorithm 1 iteration: swell, then
 bin + migration pass + global check until a pass leaves no overlap, or a
 shake).  Inputs are resident in HBM before timing starts.
 
+Timed window: the K = --steps sweeps that END at the target fraction (the
+densest sweeps of the run).  An untimed run first finds how many sweeps the
+run takes (and counts the trial moves of every sweep); a second, identical
+run (results are a pure function of the inputs) then sweeps untimed up to
+the window -- at least --warmup sweeps -- and times exactly the K window
+sweeps between two device synchronisations.  When the run is shorter than
+warmup + K sweeps the window continues past the target with sweeps at the
+target fraction.
+
 value = particle updates per second = N * (migration passes in the timed
 sweeps) / wall time of the timed sweeps.
 
@@ -39,7 +48,10 @@ ALG_BYTES_PER_UPDATE = 24 + 4 + 24
 PHASE_READ_PER_PARTICLE = 24 + 4
 PHASE_READ_PER_CELL = 4
 PHASE_WRITE_PER_OWN = 24 + 1
-BIN_BYTES = (24 + 4 + 4 + 4) + (24 + 4 + 4 + 4 + 4 + 24 + 4) + 4  # count pass + scatter + fix-up
+# Algorithmic bytes per particle update of a whole sweep step: a rebin
+# (read position and id, write them sorted, cell ranges amortised: about
+# 60 B) plus the migration pass (52 B).
+ALG_BYTES_PER_UPDATE_SWEEP = 112
 
 
 # Sources of the migration kernels: HBM traffic recorded from counters is
@@ -133,21 +145,28 @@ def recorded_platelet_valu(launch_s):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=110)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-fraction", type=float, default=0.25,
-                    help="fraction of the cell layers the oracle sample covers")
+    ap.add_argument("--cpu-n", type=int, default=0,
+                    help="particles of the oracle's sub-box (default: the box of edge 32/178 "
+                         "at the workload's number density)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-ensemble and gradient measurements")
-    ap.add_argument("--extras", default="n_scaling,platelets,platelet_protocol,batched,gradient",
+    ap.add_argument("--extras",
+                    default="at_target,n_scaling,platelets,platelet_protocol,batched,gradient",
                     help="comma-separated extras to run")
     ap.add_argument("--batch-sweeps", type=int, default=400,
                     help="sweep budget of every RVE of the batched ensemble")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="copy this many MiB device to device before the sweeps (a plain copy "
                          "kernel of known size, to calibrate HBM byte counters)")
+    ap.add_argument("--save-window", default="",
+                    help="write the state at the start of the timed window to this .npz file")
+    ap.add_argument("--window-from", default="",
+                    help="start from a state written by --save-window and run only the timed "
+                         "window (for a profiler run that sees the window's kernels alone)")
     return ap.parse_args()
 
 
@@ -176,30 +195,62 @@ def host_boundary(srm, w, torch):
             "init_from_device_s": t4 - t3, "position_bytes_each_way": int(w.pos.nbytes)}
 
 
-def cpu_baseline(w, frac):
-    """The oracle (single-threaded C) on a bounded sample of the same
-    workload: the first migration pass of sweep 1, restricted to the cells of
-    the first `frac` of the z layers."""
-    import numpy as np
-    import oracle
+def _cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_allowed": allowed}
 
+
+def cpu_baseline(steps, warmup, n_sub):
+    """The oracle (single-threaded C) on a bounded sample of the same
+    workload: a sub-box of edge L' at the same number density (1e7 per unit
+    volume), so the same target radius, migration step, rates and cell
+    occupancy, grown by the oracle itself from its own uniform start to
+    f = 0.35 with every sweep timed; the sample is the same window as the
+    GPU's, the K sweeps ending at the target (whole sweeps: swell, binning,
+    passes, global checks)."""
+    import oracle
+    import srm_inputs
+
+    L = (n_sub / 1e7) ** (1.0 / 3.0)
+    w = srm_inputs.make("spheres3d", n=n_sub, seed=1, box=(L, L, L))
     o = oracle.Oracle.from_workload(w)
-    s1 = o.swell(o.s)
-    na, inv = o.grid_for_scale(s1)
-    nz = int(na[2])
-    layers = max(1, int(nz * frac))
-    ncell = int(na[0] * na[1] * na[2])
-    mask = np.zeros(ncell, dtype=np.uint8)
-    mask[: int(na[0] * na[1] * layers)] = 1
-    cell = o.bin(na, inv)
-    updates = int(mask[cell].sum())
-    t0 = time.perf_counter()
-    o.pass_(na, inv, s1, 0, 1, mask=mask)
-    dt = time.perf_counter() - t0
-    return dict(value=updates / dt, unit="particle-updates/s", cores=1, kind="oracle",
-                sample=f"sweep 1, pass 1 of the same N={w.n} workload restricted to "
-                       f"{layers}/{nz} cell layers ({updates} particle updates, "
-                       f"{dt:.1f} s incl. binning all N), single-threaded C oracle")
+    rows, reached = [], None
+    t_all = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        info, _ = o.sweep()
+        rows.append((time.perf_counter() - t0, info["passes_main"] + info["passes_shake"]))
+        if reached is None and o.s == w.s_target:
+            reached = len(rows)
+        if reached is not None and len(rows) >= max(reached, warmup + steps):
+            break
+        if len(rows) > 5000:
+            raise RuntimeError("oracle sub-box did not reach the target")
+    start = max(warmup, reached - steps)
+    win = rows[start:start + steps]
+    dt = sum(r[0] for r in win)
+    passes = sum(r[1] for r in win)
+    return dict(value=n_sub * passes / dt, unit="particle-updates/s", cores=1, kind="oracle",
+                sample=(f"oracle sub-box of the same workload: N={n_sub} in a cube of edge "
+                        f"{L:.6f} (number density 1e7 per unit volume, f_target 0.35, same "
+                        f"s_target, c_w, c_m, N_k, N_l), grown by the oracle from its own "
+                        f"uniform start; timed: sweeps {start + 1}..{start + steps} of "
+                        f"{reached} (the {steps} sweeps ending at the target, {passes} passes, "
+                        f"{dt:.1f} s), whole sweeps incl. binning; whole growth "
+                        f"{time.perf_counter() - t_all:.1f} s"),
+                **_cpu_info())
 
 
 def _say(msg):
@@ -534,12 +585,52 @@ def grad_extra(steps, steer_steps):
     }
 
 
+def plan_window(srm, w, steps, warmup):
+    """The whole run, untimed, with trial moves counted per sweep: returns
+    the per-sweep records, the sweep that reaches the target, and the first
+    sweep (0-based) of the timed window, the `steps` sweeps ending there."""
+    g = srm.SRM.from_workload(w, device=True)
+    g.profile(enable=False, trials=True)
+    rows, reached, prev = [], None, 0
+    while True:
+        info = g.sweep()
+        tr = g.profile()["trials"]
+        rows.append({"passes": info["passes_main"] + info["passes_shake"], "trials": tr - prev,
+                     "committed": info["committed"], "fraction": info["fraction"],
+                     "s": info["s"]})
+        prev = tr
+        if reached is None and info["s"] == w.s_target:
+            reached = len(rows)
+        if reached is not None and len(rows) >= max(reached, warmup + steps):
+            break
+        if len(rows) > 5000:
+            raise RuntimeError("the run did not reach its target in 5000 sweeps")
+    g.close()
+    return rows, reached, max(warmup, reached - steps)
+
+
+def at_target_extra(g, n, steps, torch):
+    """`steps` further sweeps at the target fraction (swelling clamped, so
+    every sweep only migrates and checks), timed the same way."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    passes = 0
+    for _ in range(steps):
+        info = g.sweep()
+        passes += info["passes_main"] + info["passes_shake"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"sweeps": steps, "passes": passes, "s": dt, "updates_per_s": n * passes / dt,
+            "fraction": info["fraction"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
+    import numpy as np
     import torch
 
     import paper_2605_18254_amd as srm
@@ -553,40 +644,60 @@ def main():
         torch.cuda.synchronize()
         del a, b
     w = srm_inputs.make("spheres3d", n=args.n)
-    g = srm.SRM.from_workload(w, device=True)
-    for _ in range(args.warmup):
-        g.sweep()
+    rows, t_prefix = None, None
+    if args.window_from:
+        z = np.load(args.window_from)
+        start, reached = int(z["start"]), int(z["reached"])
+        g = srm.SRM.from_workload(w, device=True, pos=torch.from_numpy(z["pos"]).cuda(),
+                                  s0=float(z["s"]), sweep0=int(z["t"]))
+        frac_before = float(z["fraction"])
+        _say(f"window replay from sweep {start}")
+    else:
+        rows, reached, start = plan_window(srm, w, args.steps, args.warmup)
+        _say(f"target reached at sweep {reached}; window sweeps {start + 1}..{start + args.steps}")
+        g = srm.SRM.from_workload(w, device=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(start):
+            g.sweep()
+        torch.cuda.synchronize()
+        t_prefix = time.perf_counter() - t0
+        frac_before = rows[start - 1]["fraction"] if start > 0 else 0.0
+        if args.save_window:
+            pos, _, s_w, t_w = g.state()
+            np.savez(args.save_window, pos=pos, s=s_w, t=t_w, start=start, reached=reached,
+                     fraction=frac_before)
     g.profile(enable=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     passes = shakes = 0
-    phase_bytes = 0  # algorithmic bytes of all timed colour phases
+    phase_bytes = 0  # floor of the timed colour phases' real traffic
     for step in range(args.steps):
         info = g.sweep()
         npass = info["passes_main"] + info["passes_shake"]
         ncell = info["grid"][0] * info["grid"][1] * info["grid"][2]
         phase_bytes += npass * (8 * (PHASE_READ_PER_PARTICLE * w.n + PHASE_READ_PER_CELL * ncell)
                                 + PHASE_WRITE_PER_OWN * w.n)
-        if step % 25 == 24:
-            _say(f"sweep {step + 1}/{args.steps}")
-        passes += info["passes_main"] + info["passes_shake"]
+        passes += npass
         shakes += 0 if info["committed"] else 1
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = g.profile()
     final = info
+    trials = None
+    if rows is not None:
+        win = rows[start:start + args.steps]
+        if passes != sum(r["passes"] for r in win) or final["fraction"] != win[-1]["fraction"]:
+            raise RuntimeError("the timed run departed from the planning run")
+        trials = sum(r["trials"] for r in win)
+    names = [] if (args.no_extras or args.window_from) else [x for x in args.extras.split(",") if x]
+    at_target = None
+    if "at_target" in names:
+        g.profile(enable=False)
+        at_target = at_target_extra(g, w.n, args.steps, torch)
+        _say(f"at target: {at_target}")
     g.close()
-    # trial moves of the same sweeps, counted on an identical untimed replay
-    # (the count is a reduction per pass, kept out of the timed region)
-    g = srm.SRM.from_workload(w, device=True)
-    for _ in range(args.warmup):
-        g.sweep()
-    g.profile(enable=False, trials=True)
-    for _ in range(args.steps):
-        g.sweep()
-    trials = g.profile()["trials"]
-    g.close()
-    boundary = host_boundary(srm, w, torch)
+    boundary = None if args.window_from else host_boundary(srm, w, torch)
 
     updates = w.n * passes
     value = updates / dt
@@ -603,6 +714,11 @@ def main():
     bytes_per_launch = ALG_BYTES_PER_UPDATE * upd_per_launch
     achieved_gbs = bytes_per_launch / avg_launch_s / 1e9
     floor_per_launch = phase_bytes / launches
+    sweep_bytes = ALG_BYTES_PER_UPDATE_SWEEP * updates
+    window = {"first_sweep": start + 1, "last_sweep": start + args.steps,
+              "target_reached_at_sweep": reached,
+              "sweeps_past_target": max(0, start + args.steps - reached),
+              "fraction_before": frac_before, "fraction_after": final["fraction"]}
     out = {
         "metric": "particle-updates/sec per SRM sweep (N=1e7 3D)",
         "value": value,
@@ -617,9 +733,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"spheres3d N={w.n} f_target=0.35 c_w=0.01 c_m=0.1*s_target "
-                               "N_k=N_l=8 seed=1", "n": w.n, "dim": 3,
-                   "passes": passes, "shakes": shakes, "final_fraction": final["fraction"],
-                   "final_sweep": final["sweep"], "grid": list(final["grid"])},
+                               "N_k=N_l=8 seed=1; timed: the sweeps ending at the target",
+                   "n": w.n, "dim": 3, "passes": passes, "shakes": shakes,
+                   "final_fraction": final["fraction"], "final_sweep": final["sweep"],
+                   "grid": list(final["grid"]), "window": window},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
                      "traffic": traffic["bytes_per_launch"] if traffic else None,
@@ -631,30 +748,37 @@ def main():
                      "phase_floor_gbs": floor_per_launch / avg_launch_s / 1e9,
                      "traffic_source": traffic["source"] if traffic else None},
         "valu": recorded_valu(main_name, avg_launch_s),
-        "trial_moves_per_s": trials / dt,
-        "trials_per_update": trials / max(updates, 1),
+        "trial_moves_per_s": None if trials is None else trials / dt,
+        "trials_per_update": None if trials is None else trials / max(updates, 1),
         "kernel_ms": {"bin": prof["ms_bin"], "migrate": mig_ms, "check": prof["ms_check"],
                       "wall": dt * 1e3},
-        "hbm_sweep": {"alg_bytes": phase_bytes + BIN_BYTES * w.n * passes,
-                      "achieved_gbs": (phase_bytes + BIN_BYTES * w.n * passes) / dt / 1e9,
-                      "frac": (phase_bytes + BIN_BYTES * w.n * passes) / dt / 1e9 / HBM_PEAK_GBS},
+        "hbm_sweep": {"alg_bytes_per_update": ALG_BYTES_PER_UPDATE_SWEEP,
+                      "alg_bytes": sweep_bytes, "achieved_gbs": sweep_bytes / dt / 1e9,
+                      "frac": sweep_bytes / dt / 1e9 / HBM_PEAK_GBS},
     }
-    boundary["value_pcie_inclusive"] = updates / (dt + boundary["init_from_host_s"] +
-                                                  boundary["state_to_host_s"])
-    out["host_boundary"] = boundary
-    if not args.no_extras:
+    if t_prefix is not None and start + args.steps == reached:
+        run_passes = sum(r["passes"] for r in rows[:reached])
+        out["whole_run"] = {"sweeps": reached, "passes": run_passes, "s": t_prefix + dt,
+                            "updates_per_s": w.n * run_passes / (t_prefix + dt)}
+    if boundary is not None:
+        boundary["value_pcie_inclusive"] = updates / (dt + boundary["init_from_host_s"] +
+                                                      boundary["state_to_host_s"])
+        out["host_boundary"] = boundary
+    if names:
         runs = {"n_scaling": n_scaling_extra,
                 "platelets": lambda: platelet_extra(3000),
                 "platelet_protocol": platelet_protocol_extra,
                 "batched": lambda: batched_extra(args.batch_sweeps),
                 "gradient": lambda: grad_extra(20, 10)}
-        names = [x for x in args.extras.split(",") if x]
-        unknown = [x for x in names if x not in runs]
+        unknown = [x for x in names if x not in runs and x != "at_target"]
         if unknown:
             raise SystemExit(f"unknown extras: {unknown}")
-        out["extras"] = {x: runs[x]() for x in names}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_fraction)
+        out["extras"] = {x: runs[x]() for x in names if x != "at_target"}
+        if at_target is not None:
+            out["extras"]["at_target"] = at_target
+    if not args.no_cpu_baseline and not args.window_from:
+        n_sub = args.cpu_n or int(round(1e7 * (32.0 / 178.0) ** 3))
+        out["cpu_baseline"] = cpu_baseline(args.steps, args.warmup, n_sub)
     print(json.dumps(out), flush=True)
 
 
