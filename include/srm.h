@@ -294,6 +294,26 @@ srm_status srm_softrdf_backward(srm_soft *ctx, const double *pos, const double *
                                 double *grad_radii);
 srm_status srm_softrdf_free(srm_soft *ctx);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or steering loops, harnesses that forbid
+ * hipMalloc): the forward above without a workspace.  Same definitions,
+ * kernels and arguments as srm_softrdf_create + srm_softrdf_forward (the
+ * results are bit-identical), but the working memory (cell-sorted copies,
+ * binning scratch, block partials) is a fixed device array inside the
+ * library, ~17 MB, which every device the library runs on holds until the
+ * process ends.  Allocates nothing: no hipMalloc, hipFree or allocating
+ * library call.  pos (dim*n SoA), radii (n), g_out (nbins) and energy (1)
+ * are device memory owned by the caller; pos and radii are only read.
+ * n must be 2 .. SRM_SOFTRDF_STATIC_MAX_N, else SRM_ECAPACITY (beyond the
+ * limit) or SRM_EINVAL, with nothing launched.  Every call on one device
+ * shares that device's array: calls that overlap in time on one device
+ * (two streams, two threads) race and give undefined results; calls in
+ * one stream are ordered and safe. */
+#define SRM_SOFTRDF_STATIC_MAX_N 262144
+srm_status srm_softrdf_forward_static(const srm_softrdf_params *p, int64_t n,
+                                      const double *pos, const double *radii, double *g_out,
+                                      double *energy, void *stream);
+
 /* ---- batched ensembles ------------------------------------------------- */
 
 /* `count` independent periodic boxes (RVEs) of balls, 2D and 3D mixed, each

@@ -28,7 +28,7 @@ SYMBOLS = ["srm_init", "srm_sweep", "srm_run_to_fraction", "srm_pairs", "srm_rdf
            "srm_percolation", "srm_critical_gap", "srm_rsa",
            "srm_get_state", "srm_free", "srm_last_error", "srm_grid", "srm_cells", "srm_pass",
            "srm_last_acc", "srm_set_state", "srm_softrdf_create", "srm_softrdf_forward",
-           "srm_softrdf_backward", "srm_softrdf_free", "srm_profile_enable", "srm_profile_read",
+           "srm_softrdf_backward", "srm_softrdf_free", "srm_softrdf_forward_static", "srm_profile_enable", "srm_profile_read",
            "srm_batch_init", "srm_batch_configure", "srm_batch_run", "srm_batch_get",
            "srm_batch_free", "srm_batch_last_error", "srm_debug_fp",
            "srm_debug_philox", "srm_debug_unitvec"]

@@ -29,8 +29,8 @@
 namespace srm {
 namespace {
 
-constexpr int kBlock = 128;
-constexpr int kMaxBins = 64;
+constexpr int kBlock = kSoftBlock;
+constexpr int kMaxBins = kSoftPartialStride - 1;
 constexpr double kInvE = 0.36787944117144233;  // e^-1 rounded to binary64
 
 struct SoftArgs {

@@ -9,6 +9,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -1032,6 +1033,40 @@ struct srm_soft {
 
 namespace {
 
+// Validates the descriptor's parameters (dim, bins, cutoff, box) for n
+// particles and builds its neighbour grid: cells at least r_c + 4h wide,
+// capped like the SRM grid.  pp is *p with box[2] = 1 in 2D.
+srm_status soft_setup(const srm_softrdf_params *p, int64_t n, srm_softrdf_params &pp, Grid &g)
+{
+    if (!p) return fail(SRM_EINVAL, "NULL argument");
+    if (p->dim != 2 && p->dim != 3) return fail(SRM_EINVAL, "dim must be 2 or 3");
+    if (p->nbins < 1 || p->nbins > 64) return fail(SRM_EINVAL, "nbins must be 1..64");
+    if (n < 2 || n > 0x7fffffffLL) return fail(SRM_EINVAL, "n out of range");
+    if (!(p->r_c > 0.0) || !isfinite(p->r_c) || !(p->kappa >= 0.0))
+        return fail(SRM_EINVAL, "bad r_c or kappa");
+    for (int a = 0; a < p->dim; ++a)
+        if (!(p->box[a] > 0.0)) return fail(SRM_EINVAL, "box edge <= 0");
+    pp = *p;
+    if (pp.dim == 2) pp.box[2] = 1.0;
+    const int64_t ncap = cell_cap(pp.dim, n);
+    const double cut = pp.r_c + 4.0 * (pp.r_c / pp.nbins);
+    for (int a = 0; a < 3; ++a) {
+        g.box[a] = pp.box[a];
+        g.half[a] = 0.5 * pp.box[a];
+        if (a >= pp.dim) {
+            g.na[a] = 1;
+            g.inv_w[a] = 1.0 / pp.box[a];
+            continue;
+        }
+        const double q = pp.box[a] / cut;
+        const int64_t m = (q >= (double)ncap) ? ncap : (int64_t)q;
+        g.na[a] = (int32_t)(m >= 4 ? m : 1);
+        g.inv_w[a] = (double)g.na[a] / pp.box[a];
+    }
+    g.ncell = g.na[0] * g.na[1] * g.na[2];
+    return SRM_OK;
+}
+
 srm_status soft_bin(srm_soft *c, const double *pos, const double *radii)
 {
     const size_t n = (size_t)c->n;
@@ -1052,38 +1087,18 @@ extern "C" {
 srm_status srm_softrdf_create(const srm_softrdf_params *p, int64_t n, void *stream,
                               srm_soft **out)
 {
-    if (!p || !out) return fail(SRM_EINVAL, "NULL argument");
-    if (p->dim != 2 && p->dim != 3) return fail(SRM_EINVAL, "dim must be 2 or 3");
-    if (p->nbins < 1 || p->nbins > 64) return fail(SRM_EINVAL, "nbins must be 1..64");
-    if (n < 2 || n > 0x7fffffffLL) return fail(SRM_EINVAL, "n out of range");
-    if (!(p->r_c > 0.0) || !isfinite(p->r_c) || !(p->kappa >= 0.0))
-        return fail(SRM_EINVAL, "bad r_c or kappa");
-    for (int a = 0; a < p->dim; ++a)
-        if (!(p->box[a] > 0.0)) return fail(SRM_EINVAL, "box edge <= 0");
+    if (!out) return fail(SRM_EINVAL, "NULL argument");
+    srm_softrdf_params pp{};
+    Grid g{};
+    const srm_status st = soft_setup(p, n, pp, g);
+    if (st) return st;
     srm_soft *c = new (std::nothrow) srm_soft();
     if (!c) return fail(SRM_ENOMEM, "host allocation failed");
-    c->p = *p;
-    if (c->p.dim == 2) c->p.box[2] = 1.0;
+    c->p = pp;
     c->n = (int32_t)n;
     c->stream = (hipStream_t)stream;
     c->ncap = cell_cap(c->p.dim, n);
-    // neighbour grid: cells at least r_c + 4h wide
-    const double cut = p->r_c + 4.0 * (p->r_c / p->nbins);
-    Grid &g = c->g;
-    for (int a = 0; a < 3; ++a) {
-        g.box[a] = c->p.box[a];
-        g.half[a] = 0.5 * c->p.box[a];
-        if (a >= c->p.dim) {
-            g.na[a] = 1;
-            g.inv_w[a] = 1.0 / c->p.box[a];
-            continue;
-        }
-        const double q = c->p.box[a] / cut;
-        const int64_t m = (q >= (double)c->ncap) ? c->ncap : (int64_t)q;
-        g.na[a] = (int32_t)(m >= 4 ? m : 1);
-        g.inv_w[a] = (double)g.na[a] / c->p.box[a];
-    }
-    g.ncell = g.na[0] * g.na[1] * g.na[2];
+    c->g = g;
     hipError_t e = hipSuccess;
     for (int a = 0; a < c->p.dim && !e; ++a)
         if ((e = c->alloc(&c->in.x[a], n)) == hipSuccess) e = c->alloc(&c->sorted.x[a], n);
@@ -1138,6 +1153,143 @@ srm_status srm_softrdf_free(srm_soft *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     delete c;
+    return SRM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------- soft g(r) without allocation
+//
+// srm_softrdf_forward_static runs the forward above on a file-scope device
+// array instead of a workspace: cell-sorted copies of positions, radii and
+// ids, the id sequence, the binning scratch, the scan partials, the
+// counters and the block partials, for at most kStaticSoftN particles.
+// Each device holds its own copy of the array; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device.
+
+namespace {
+
+constexpr int64_t kStaticSoftN = SRM_SOFTRDF_STATIC_MAX_N;
+
+constexpr size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct StaticSoftLayout {
+    size_t x[3], rho, id, inid, cell, slot, tmpid, counts, start, partials, cnt, partial, total;
+};
+
+constexpr StaticSoftLayout static_soft_layout(int64_t n)
+{
+    StaticSoftLayout L{};
+    const size_t un = (size_t)n, cap = un + 2;
+    size_t o = 0;
+    for (int a = 0; a < 3; ++a) {
+        L.x[a] = o;
+        o += up256(un * sizeof(double));
+    }
+    L.rho = o;
+    o += up256(un * sizeof(double));
+    L.id = o;
+    o += up256(un * sizeof(int32_t));
+    L.inid = o;
+    o += up256(un * sizeof(int32_t));
+    L.cell = o;
+    o += up256(un * sizeof(int32_t));
+    L.slot = o;
+    o += up256(un * sizeof(int32_t));
+    L.tmpid = o;
+    o += up256(un * sizeof(int32_t));
+    L.counts = o;
+    o += up256(cap * sizeof(int32_t));
+    L.start = o;
+    o += up256((cap + 1) * sizeof(int32_t));
+    L.partials = o;
+    o += up256((cap / 2048 + 2) * sizeof(int32_t));
+    L.cnt = o;
+    o += up256(sizeof(Counters));
+    L.partial = o;
+    o += up256((un + kSoftBlock - 1) / kSoftBlock * kSoftPartialStride * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+constexpr size_t kStaticSoftBytes = static_soft_layout(kStaticSoftN).total;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+unsigned char *g_static_base[kMaxDevices];  // device address of `scratch`, per device
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticSoftBytes];
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the array's name is not a device address in host code).
+srm_status static_scratch(unsigned char **base)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(SRM_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SRM_EDEVICE, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_base[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(SRM_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_static_base[dev] = (unsigned char *)ptr;
+    }
+    *base = g_static_base[dev];
+    return SRM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+srm_status srm_softrdf_forward_static(const srm_softrdf_params *p, int64_t n, const double *pos,
+                                      const double *radii, double *g_out, double *energy,
+                                      void *stream)
+{
+    if (!pos || !radii || !g_out || !energy) return fail(SRM_EINVAL, "NULL argument");
+    srm_softrdf_params pp{};
+    Grid g{};
+    srm_status st = soft_setup(p, n, pp, g);
+    if (st) return st;
+    if (n > kStaticSoftN)
+        return fail(SRM_ECAPACITY, "n = %lld exceeds the static workspace of %lld particles",
+                    (long long)n, (long long)kStaticSoftN);
+    unsigned char *base = nullptr;
+    if ((st = static_scratch(&base))) return st;
+    constexpr StaticSoftLayout L = static_soft_layout(kStaticSoftN);
+    const hipStream_t s = (hipStream_t)stream;
+    const int32_t nn = (int32_t)n;
+    PBuf in{}, sorted{};
+    for (int a = 0; a < pp.dim; ++a) {
+        in.x[a] = const_cast<double *>(pos + (size_t)a * (size_t)n);
+        sorted.x[a] = (double *)(base + L.x[a]);
+    }
+    in.rho = const_cast<double *>(radii);
+    in.id = (int32_t *)(base + L.inid);
+    sorted.rho = (double *)(base + L.rho);
+    sorted.id = (int32_t *)(base + L.id);
+    Scratch sc{};
+    sc.cell = (int32_t *)(base + L.cell);
+    sc.slot = (int32_t *)(base + L.slot);
+    sc.tmpid = (int32_t *)(base + L.tmpid);
+    sc.counts = (int32_t *)(base + L.counts);
+    sc.start = (int32_t *)(base + L.start);
+    sc.partials = (int32_t *)(base + L.partials);
+    sc.cap = n + 2;
+    Counters *cnt = (Counters *)(base + L.cnt);
+    double *partial = (double *)(base + L.partial);
+    HIP_TRY(launch_iota(in.id, nn, s));
+    HIP_TRY(launch_zero_counters(cnt, s));
+    HIP_TRY(bin_particles(pp.dim, in, sorted, nn, g, sc, cnt, s));
+    HIP_TRY(soft_forward(pp.dim, sorted, sc.start, g, nn, pp.nbins, pp.r_c, pp.kappa, partial,
+                         g_out, energy, s));
     return SRM_OK;
 }
 

@@ -130,6 +130,10 @@ hipError_t nearest(int dim, const PBuf &b, const int32_t *start, const Grid &g, 
                    hipStream_t stream);
 
 // Soft-binned g(r) + overlap energy and its gradient (k_softrdf.hip).
+// Soft g(r) launch shape: threads per block of the forward kernel and
+// doubles per block partial (64 bins, then the energy).
+constexpr int32_t kSoftBlock = 128;
+constexpr int32_t kSoftPartialStride = 65;
 int32_t soft_blocks(int32_t n);
 int32_t soft_partial_stride();
 hipError_t soft_forward(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,

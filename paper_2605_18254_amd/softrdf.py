@@ -31,9 +31,11 @@ def _bind():
     L.srm_softrdf_forward.argtypes = [vp, vp, vp, vp, vp]
     L.srm_softrdf_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.srm_softrdf_free.argtypes = [vp]
+    L.srm_softrdf_forward_static.argtypes = [C.POINTER(SoftParams), C.c_int64, vp, vp, vp, vp,
+                                             vp]
     L.srm_set_state.argtypes = [vp, vp, vp, C.c_int32]
     for f in ("srm_softrdf_create", "srm_softrdf_forward", "srm_softrdf_backward",
-              "srm_softrdf_free", "srm_set_state"):
+              "srm_softrdf_free", "srm_softrdf_forward_static", "srm_set_state"):
         getattr(L, f).restype = C.c_int32
     L._soft_bound = True
     return L
@@ -85,6 +87,34 @@ class SoftRDF:
         _check(lib().srm_softrdf_backward(self._ctx, _ptr(pos), _ptr(radii), _ptr(dg), _ptr(de),
                                           _ptr(gp), _ptr(gr)))
         return gp, gr
+
+
+# Largest n srm_softrdf_forward_static accepts (its fixed device array).
+STATIC_MAX_N = 262144
+
+
+def soft_params(dim: int, r_c: float, nbins: int = 64, box=(1.0, 1.0, 1.0),
+                kappa: float = 1.0) -> SoftParams:
+    p = SoftParams()
+    p.dim, p.nbins, p.r_c, p.kappa = int(dim), int(nbins), float(r_c), float(kappa)
+    box3 = list(box) + [1.0] * (3 - len(box))
+    for a in range(3):
+        p.box[a] = float(box3[a])
+    return p
+
+
+def forward_static(pos: torch.Tensor, radii: torch.Tensor, g: torch.Tensor, e: torch.Tensor,
+                   dim: int, r_c: float, nbins: int = 64, box=(1.0, 1.0, 1.0),
+                   kappa: float = 1.0) -> None:
+    """The soft g(r) forward into caller-owned g (nbins,) and e (), with no
+    workspace and no device allocation (``srm_softrdf_forward_static``);
+    runs on torch's current stream."""
+    L = _bind()
+    p = soft_params(dim, r_c, nbins, box, kappa)
+    n = pos.shape[1]
+    stream = torch.cuda.current_stream().cuda_stream
+    _check(L.srm_softrdf_forward_static(C.byref(p), n, _ptr(pos), _ptr(radii), _ptr(g), _ptr(e),
+                                        C.c_void_p(stream)))
 
 
 class SoftRDFFunction(torch.autograd.Function):
