@@ -155,7 +155,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-ensemble and gradient measurements")
     ap.add_argument("--extras",
-                    default="at_target,n_scaling,platelets,platelet_protocol,batched,gradient",
+                    default="at_target,n_scaling,platelets,platelet_protocol,spherodisk_protocol,"
+                            "batched,gradient",
                     help="comma-separated extras to run")
     ap.add_argument("--batch-sweeps", type=int, default=400,
                     help="sweep budget of every RVE of the batched ensemble")
@@ -501,6 +502,98 @@ def platelet_protocol_extra(densities=(1.0, 2.0, 5.0), n=20_000, relax_sweeps=10
                         f"relax: c_w 0, c_m 0.5 a_t, {relax_sweeps} sweeps; RSA at the same "
                         f"density", "runs": rows}
 
+def spherodisk_protocol_extra(densities=(1.0, 2.0, 5.0), aspect_ratios=(100.0, 200.0),
+                              n=20_000, relax_sweeps=100, dense_rho=30.0, dense_budget_s=60.0):
+    """Sec. 3.3 with the paper's platelet model: 20000 spherodisks of aspect
+    ratio 100 and 200 at number density rho = N D^3 / L^3, grown into
+    house-of-cards networks (c_w = 0.02, c_m = 0.1 a_t) and relaxed (no
+    swelling, c_m = 0.5 a_t, `relax_sweeps` sweeps); the critical
+    percolation distance delta_c / D of both (hard core - soft shell: bonded
+    when the core disks come within t + delta, 30 bisection steps).  Then
+    the densification of Fig. 10: the relaxed aspect-ratio-100 state at the
+    highest density swollen toward rho = `dense_rho` (c_w = 0.002,
+    c_m = 0.2 a, N_l = 16) for at most `dense_budget_s` seconds."""
+    import torch
+
+    import paper_2605_18254_amd as srm
+    import srm_inputs
+
+    def gap_c(g, diam):
+        hi = 0.05 * diam
+        while not g.percolation(hi) and hi < 8 * diam:
+            hi *= 2.0
+        return g.critical_gap(0.0, hi, 30) / diam if g.percolation(hi) else None
+
+    def make(ar, rho, **kw):
+        tau = 1.0 / ar
+        f = srm_inputs.spherodisk_volume_coeff(tau) * rho / 8.0  # N v (D/2)^3 / L^3
+        return srm_inputs.make("spherodisks", n=n, seed=11, aspect_ratio=ar, f_target=f, **kw)
+
+    rows, dense = [], None
+    for ar in aspect_ratios:
+        for rho in densities:
+            w = make(ar, rho, c_w=0.02, c_m_rel=0.1)
+            diam = 2.0 * w.s_target
+            g = srm.SRM.from_workload(w, device=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, info = g.run(2000)
+            torch.cuda.synchronize()
+            t_hoc = time.perf_counter() - t0
+            hoc = gap_c(g, diam)
+            pos, nrm, s_fin, t_fin = g.state()
+            g.close()
+            c_m = 0.5 * w.s_target
+            r = srm.SRM(dim=3, n=n, s_target=w.s_target, c_w=0.0, c_m=c_m, n_k=8, n_l=8,
+                        seed=w.seed, pos=pos, normals=nrm, shape=srm.SPHERODISK,
+                        c_n=c_m / w.s_target, thick_ratio=w.thick_ratio, s0=s_fin, sweep0=t_fin)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(relax_sweeps):
+                r.sweep()
+            torch.cuda.synchronize()
+            t_rel = time.perf_counter() - t0
+            rel = gap_c(r, diam)
+            overlaps = len(r.pairs(0.0))
+            rows.append({"aspect_ratio": ar, "rho": rho, "f": w.f_target, "converged": st == 0,
+                         "grow_sweeps": info["sweeps"], "grow_s": t_hoc, "relax_s": t_rel,
+                         "delta_c_over_d_grown": hoc, "delta_c_over_d_relaxed": rel,
+                         "ratio_relaxed_to_grown": (rel / hoc) if (hoc and rel) else None,
+                         "overlapping_pairs": overlaps})
+            _say(f"spherodisk protocol: {rows[-1]}")
+            if ar == aspect_ratios[0] and rho == max(densities) and dense_rho > rho:
+                # densification: swell the relaxed state toward dense_rho
+                pos, nrm, s_rel, t_rel_sw = r.state()
+                s_dense = s_rel * (dense_rho / rho) ** (1.0 / 3.0)
+                c_m = 0.2 * s_rel
+                d = srm.SRM(dim=3, n=n, s_target=s_dense, c_w=0.002, c_m=c_m, n_k=8, n_l=16,
+                            seed=w.seed, pos=pos, normals=nrm, shape=srm.SPHERODISK,
+                            c_n=c_m / s_rel, thick_ratio=w.thick_ratio, s0=s_rel,
+                            sweep0=t_rel_sw)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sweeps = 0
+                info_d = None
+                while time.perf_counter() - t0 < dense_budget_s:
+                    info_d = d.sweep()
+                    sweeps += 1
+                    if info_d["s"] == s_dense:
+                        break
+                torch.cuda.synchronize()
+                s_now = info_d["s"] if info_d else s_rel
+                dense = {"from_rho": rho, "target_rho": dense_rho,
+                         "reached_rho": n * (2.0 * s_now) ** 3, "sweeps": sweeps,
+                         "s": time.perf_counter() - t0, "fraction": info_d["fraction"] if info_d else None,
+                         "overlapping_pairs": len(d.pairs(0.0)),
+                         "delta_c_over_d": gap_c(d, 2.0 * s_now)}
+                d.close()
+                _say(f"spherodisk densification: {dense}")
+            r.close()
+    return {"workload": f"{n} spherodisks (outer diameter D, thickness D / aspect ratio), seed "
+                        f"11; grown: c_w 0.02, c_m 0.1 a_t; relax: c_w 0, c_m 0.5 a_t, "
+                        f"{relax_sweeps} sweeps", "runs": rows, "densification": dense}
+
+
 def grad_extra(steps, steer_steps):
     """Soft g(r) (64 Gaussian bins up to 5r) + overlap energy, forward and
     hand-written backward, on N = 2e5 spheres grown by SRM to f = 0.30; then
@@ -768,6 +861,7 @@ def main():
         runs = {"n_scaling": n_scaling_extra,
                 "platelets": lambda: platelet_extra(3000),
                 "platelet_protocol": platelet_protocol_extra,
+                "spherodisk_protocol": spherodisk_protocol_extra,
                 "batched": lambda: batched_extra(args.batch_sweeps),
                 "gradient": lambda: grad_extra(20, 10)}
         unknown = [x for x in names if x not in runs and x != "at_target"]

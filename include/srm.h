@@ -51,7 +51,15 @@ enum {
     SRM_ECAPACITY = -6   /* output buffer too small; *count holds the need */
 };
 
-enum { SRM_BALL = 0, SRM_PLATELET = 1 };
+/* Particle shapes.  SRM_PLATELET: zero-thickness circular disks (exact
+ * disk-disk intersection).  SRM_SPHERODISK: the thin circular platelets of
+ * Sec. 3.3 as spherodisks -- every point within h of a flat core disk of
+ * radius A; a particle of outer radius a = s rho has h = thick_ratio a
+ * (thickness t = thick_ratio D, D = 2a) and A = a - h.  Two spherodisks
+ * overlap iff the minimum distance between their core disks is at most
+ * h_i + h_j (touching counts), decided within 1e-12 (A_i + A_j) of that
+ * bound, where it counts as overlap. */
+enum { SRM_BALL = 0, SRM_PLATELET = 1, SRM_SPHERODISK = 2 };
 enum { SRM_MEM_HOST = 0, SRM_MEM_DEVICE = 1 };
 enum { SRM_PASS_MAIN = 0, SRM_PASS_SHAKE = 1 };
 
@@ -61,14 +69,15 @@ enum { SRM_PASS_MAIN = 0, SRM_PASS_SHAKE = 1 };
  * s0 to s_target. */
 typedef struct {
     int32_t dim;         /* 2 (disks) or 3 (spheres, platelets) */
-    int32_t shape;       /* SRM_BALL, or SRM_PLATELET (3D only: thin disks) */
+    int32_t shape;       /* SRM_BALL, SRM_PLATELET or SRM_SPHERODISK (both 3D only) */
     int64_t n;           /* particle count, 1 <= n < 2^31 */
     double box[3];       /* periodic box edges L_a > 0 (box[2] unused in 2D) */
     double s_target;     /* final radius scale (sets the target fraction) */
     double c_w;          /* swelling step per sweep, as a fraction of s_target */
     double c_m;          /* migration step length (absolute) */
     double c_n;          /* platelet normal step (unit-vector length) */
-    double thick_ratio;  /* platelet thickness / diameter (volume only) */
+    double thick_ratio;  /* platelet thickness / diameter: volume only for SRM_PLATELET;
+                            shape and volume for SRM_SPHERODISK (0 < thick_ratio < 0.5) */
     int32_t n_k;         /* passes per sweep before a shake, 0..32767 */
     int32_t n_l;         /* trial moves per particle per pass, 0..255 */
     uint64_t seed;       /* Philox key */
@@ -117,7 +126,8 @@ srm_status srm_sweep(srm_ctx *ctx, srm_sweep_info *info);
  * (Sec. 2 step e: stop at the target fraction).  In these sweeps swelling
  * stops at the scale s_f whose fraction is f_target (to rounding:
  * s_f = (f_target |box| / (w sum_i rho_i^dim))^(1/dim), w = pi for disks,
- * 4 pi/3 for spheres, 2 pi thick_ratio for platelets), or at s_target when
+ * 4 pi/3 for spheres, 2 pi thick_ratio for platelets, 2 pi A^2 h + pi^2 A h^2 +
+ * 4/3 pi h^3 with h = thick_ratio, A = 1 - h for spherodisks), or at s_target when
  * that is smaller; f_target <= 0 means s_target itself.  An intermediate
  * target serves staged protocols (grow to f1, change the rates in a new
  * context from the saved state, continue); srm_sweep outside this call
@@ -132,7 +142,9 @@ srm_status srm_run_to_fraction(srm_ctx *ctx, double f_target, int32_t max_sweeps
  * `gap` >= 0 of each other: balls with q_ij <= ((R_i + R_j) + gap)^2 under
  * the minimum image (the hard core - soft shell contact of percolation
  * studies, Sec. 3.3); platelets whose disks, with radii grown to a + gap/2,
- * intersect (gap = 0: the admissibility test itself).  Written to ij (host
+ * intersect; spherodisks whose core disks come within h_i + h_j + gap
+ * (shells of thickness gap/2 around each surface) (gap = 0: the
+ * admissibility test itself).  Written to ij (host
  * or device per mem_kind) as (i, j) int32 pairs sorted by (i, j); *count =
  * number of pairs.  Needs 2 R_max + gap <= min(L_a)/2 (SRM_EINVAL
  * otherwise).  SRM_ECAPACITY (nothing written, *count = the number of
@@ -203,7 +215,8 @@ srm_status srm_nearest(srm_ctx *ctx, double r_max, double *dist_by_id, int32_t n
 /* Hard core - soft shell percolation (the critical percolation distance of
  * Sec. 3.3, Fig. 9): particles are bonded when they overlap after growing
  * by `gap` (the srm_pairs predicate: (R_i + R_j) + gap for balls, disk
- * radii a + gap/2 for platelets), and *wraps gets bit a set when a cluster
+ * radii a + gap/2 for platelets, core-disk distance h_i + h_j + gap for
+ * spherodisks), and *wraps gets bit a set when a cluster
  * wraps around the periodic box along axis a (a cycle of bonds whose
  * periodic images do not close along a); 0 means no cluster spans the box.
  * Needs 2 R_max + gap <= L/2.  Errors: SRM_EINVAL; SRM_ECAPACITY if a

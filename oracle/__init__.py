@@ -107,6 +107,11 @@ def lib():
         L.o_softrdf_grad.argtypes = [C.POINTER(SoftParams), C.c_int64, dp, dp, dp, C.c_double,
                                      dp, dp]
         L.o_disks_intersect.restype = C.c_int
+        L.o_sd_within.argtypes = [dp, dp, C.c_double, dp, C.c_double, C.c_double]
+        L.o_sd_within.restype = C.c_int
+        L.o_spherodisks_overlap.argtypes = [dp, dp, C.c_double, dp, dp, C.c_double, C.c_double,
+                                            C.c_double, dp]
+        L.o_spherodisks_overlap.restype = C.c_int
         L.o_rsa_candidate.argtypes = [C.c_int, C.c_int, dp, C.c_uint64, C.c_uint64, dp, dp]
         L.o_rsa.argtypes = [C.c_int, C.c_int, C.c_int64, dp, C.c_double, C.c_uint64,
                             C.c_int64, dp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
@@ -178,6 +183,24 @@ def disks_intersect(c1, n1, a1, c2, n2, a2, box=(1.0, 1.0, 1.0)) -> bool:
     arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (c1, n1, c2, n2, box)]
     return bool(lib().o_disks_intersect(_dp(arrs[0]), _dp(arrs[1]), float(a1), _dp(arrs[2]),
                                         _dp(arrs[3]), float(a2), _dp(arrs[4])))
+
+
+def sd_within(d, n1, A1, n2, A2, T) -> bool:
+    """Core disk 1 (centre 0, unit normal n1, radius A1) and core disk 2
+    (centre d, n2, A2): is their minimum distance at most T?"""
+    arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (d, n1, n2)]
+    return bool(lib().o_sd_within(_dp(arrs[0]), _dp(arrs[1]), float(A1), _dp(arrs[2]),
+                                  float(A2), float(T)))
+
+
+def spherodisks_overlap(c1, n1, a1, c2, n2, a2, thick_ratio, gap=0.0,
+                        box=(1.0, 1.0, 1.0)) -> bool:
+    """Spherodisks of outer radii a1, a2 and thickness thick_ratio * 2a
+    (lower particle id as disk 1), shells grown by gap."""
+    arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (c1, n1, c2, n2, box)]
+    return bool(lib().o_spherodisks_overlap(_dp(arrs[0]), _dp(arrs[1]), float(a1),
+                                            _dp(arrs[2]), _dp(arrs[3]), float(a2),
+                                            float(thick_ratio), float(gap), _dp(arrs[4])))
 
 
 def _soft_params(dim, nbins, r_c, box=(1.0, 1.0, 1.0), kappa=1.0):
@@ -403,6 +426,13 @@ class Oracle:
         if p.shape == 1:
             a = s * rho
             return float(np.sum(math.pi * a * a * (p.thick_ratio * 2.0 * a)) / vbox)
+        if p.shape == 2:
+            # spherodisk: core radius A = a - h, half-thickness h = thick_ratio * a
+            a = s * rho
+            h = p.thick_ratio * a
+            A = a - h
+            v = 2.0 * math.pi * A * A * h + math.pi ** 2 * A * h * h + 4.0 / 3.0 * math.pi * h ** 3
+            return float(np.sum(v) / vbox)
         w = math.pi if p.dim == 2 else 4.0 * math.pi / 3.0
         return float(w * np.sum((s * rho) ** p.dim) / vbox)
 

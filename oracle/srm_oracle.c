@@ -44,6 +44,13 @@
  *    exact disk-disk intersection (chords on the planes' common line); the
  *    centre trial and a normal trial (stream 1, step c_n) are accepted or
  *    rejected together.
+ *  - spherodisks (Sec. 3.3 names the platelet model): a particle of
+ *    diameter D = 2a and thickness t = thick_ratio * D is the set of points
+ *    within h = t/2 of a flat core disk of radius A = a - h (D is the outer
+ *    diameter, so the model tends to the zero-thickness disk as t -> 0).
+ *    Two spherodisks overlap iff the minimum distance between their core
+ *    disks is at most h_i + h_j (touching counts), tested with the lower id
+ *    as disk 1.  Volume 2 pi A^2 h + pi^2 A h^2 + 4/3 pi h^3 (Steiner).
  *  - initial configuration (Sec. 2, Alg. 1 "RSA procedure"): classical random
  *    sequential addition of equal particles.  One stream of candidates
  *    k = 0, 1, 2, ... (Philox counters (k_lo, k_hi, call, 2) for the centre,
@@ -68,6 +75,7 @@
 
 #define O_BALL 0
 #define O_PLATELET 1
+#define O_SPHERODISK 2
 
 #define O_MAIN 0
 #define O_SHAKE 1
@@ -200,15 +208,12 @@ static double o_radius(const o_state *st, double s, int64_t i)
     return st->rho ? s * st->rho[i] : s * 1.0;
 }
 
-/* Zero-thickness disk-disk intersection.  Disk 1 = (c1, n1, a1), disk 2 =
- * (c2, n2, a2); callers pass the lower particle id as disk 1. */
-int o_disks_intersect(const double c1[3], const double n1[3], double a1,
-                      const double c2[3], const double n2[3], double a2,
-                      const double box[3])
+/* Zero-thickness disk-disk intersection of disk 1 (centre 0, unit normal
+ * n1, radius a1) and disk 2 (centre d, n2, a2). */
+static int o_disks_meet(const double d[3], const double n1[3], double a1, const double n2[3],
+                        double a2)
 {
-    double dx = o_minimg(c2[0] - c1[0], box[0]);
-    double dy = o_minimg(c2[1] - c1[1], box[1]);
-    double dz = o_minimg(c2[2] - c1[2], box[2]);
+    double dx = d[0], dy = d[1], dz = d[2];
     double dd = dx * dx + dy * dy + dz * dz;
     double sa = a1 + a2;
     if (dd > sa * sa) return 0;
@@ -241,6 +246,256 @@ int o_disks_intersect(const double c1[3], const double n1[3], double a1,
     double D = (C - Ap) - Bp;
     if (D <= 0.0) return 1;
     return D * D <= (4.0 * Ap) * Bp;
+}
+
+/* The same test for disks at c1 and c2 (minimum image of c2 - c1); callers
+ * pass the lower particle id as disk 1. */
+int o_disks_intersect(const double c1[3], const double n1[3], double a1,
+                      const double c2[3], const double n2[3], double a2,
+                      const double box[3])
+{
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = o_minimg(c2[a] - c1[a], box[a]);
+    return o_disks_meet(d, n1, a1, n2, a2);
+}
+
+/* ---- spherodisks: is the distance between two core disks at most T? ----
+ * Core disk 1 has centre 0, unit normal n1, radius A1; core disk 2 has
+ * centre d, n2, A2.  The decision rests on two kinds of certificate:
+ *  - a pair of points p on disk 1 and q on disk 2 with |q - p| <= T proves
+ *    overlap;
+ *  - a unit direction u with L(u) = u.d - A1 |u x n1| - A2 |u x n2| > T
+ *    proves separation: the projections of the two disks on u are at
+ *    least L(u) apart (A |u x n| is a disk's half-extent along u), so every
+ *    pair of points is.
+ * At the closest pair (p*, q*) the direction (q* - p*)/|q* - p*| gives
+ * L = |q* - p*|, so the certificates meet at the true distance.  Pairs
+ * come from (in order) the zero-thickness intersection test, the point of
+ * each rim nearest the other disk's plane, alternating projections between
+ * the disks (which converge to a closest pair of two disjoint convex sets),
+ * and Newton's method on the two rim angles started from those pairs.
+ * Where no certificate decides -- the distance lies within 1e-12 (A1 + A2)
+ * of T, or the iterations run out -- the pair counts as overlapping, the
+ * conservative side for admissibility. */
+static double o_sd_lower(const double u[3], const double d[3], const double n1[3], double A1,
+                         const double n2[3], double A2)
+{
+    double x0 = u[1] * n1[2] - u[2] * n1[1];
+    double x1 = u[2] * n1[0] - u[0] * n1[2];
+    double x2 = u[0] * n1[1] - u[1] * n1[0];
+    double y0 = u[1] * n2[2] - u[2] * n2[1];
+    double y1 = u[2] * n2[0] - u[0] * n2[2];
+    double y2 = u[0] * n2[1] - u[1] * n2[0];
+    double e1 = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+    double e2 = sqrt(y0 * y0 + y1 * y1 + y2 * y2);
+    double ud = u[0] * d[0] + u[1] * d[1] + u[2] * d[2];
+    return (ud - A1 * e1) - A2 * e2;
+}
+
+/* Nearest point y of the disk (centre 0, unit normal n, radius A) to x;
+ * returns 1 when y lies on the rim. */
+static int o_sd_proj(const double x[3], const double n[3], double A, double y[3])
+{
+    double h = x[0] * n[0] + x[1] * n[1] + x[2] * n[2];
+    y[0] = x[0] - h * n[0];
+    y[1] = x[1] - h * n[1];
+    y[2] = x[2] - h * n[2];
+    double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+    if (r2 <= A * A) return 0;
+    double f = A / sqrt(r2);
+    y[0] = y[0] * f;
+    y[1] = y[1] * f;
+    y[2] = y[2] * f;
+    return 1;
+}
+
+#define O_SD_BAND 1e-12
+
+/* 1: overlap, 0: separated, -1: the pair (p, q) decides nothing. */
+static int o_sd_certify(const double p[3], const double q[3], const double d[3],
+                        const double n1[3], double A1, const double n2[3], double A2, double T)
+{
+    double w0 = q[0] - p[0], w1 = q[1] - p[1], w2 = q[2] - p[2];
+    double ww = w0 * w0 + w1 * w1 + w2 * w2;
+    if (ww <= T * T) return 1;
+    double ub = sqrt(ww);
+    double u[3] = {w0 / ub, w1 / ub, w2 / ub};
+    double lb = o_sd_lower(u, d, n1, A1, n2, A2);
+    if (lb > T) return 0;
+    if (ub - lb <= O_SD_BAND * (A1 + A2)) return 1;
+    return -1;
+}
+
+static void o_sd_unit(double v[3])
+{
+    double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] = v[0] / r;
+    v[1] = v[1] / r;
+    v[2] = v[2] / r;
+}
+
+/* Newton's method on the squared distance between the rim points A1 r1
+ * and d + A2 r2 (r1, r2 unit vectors in the disks' planes), each step
+ * rotating r1, r2 by the solved angles (r + s t, renormalised, t = n x r).
+ * Stops where the Hessian is not positive definite. */
+static int o_sd_newton(const double d[3], const double n1[3], double A1, const double n2[3],
+                       double A2, double T, const double r1_in[3], const double r2_in[3])
+{
+    double r1[3] = {r1_in[0], r1_in[1], r1_in[2]}, r2[3] = {r2_in[0], r2_in[1], r2_in[2]};
+    for (int j = 0; j < 8; ++j) {
+        double t1[3] = {n1[1] * r1[2] - n1[2] * r1[1], n1[2] * r1[0] - n1[0] * r1[2],
+                        n1[0] * r1[1] - n1[1] * r1[0]};
+        double t2[3] = {n2[1] * r2[2] - n2[2] * r2[1], n2[2] * r2[0] - n2[0] * r2[2],
+                        n2[0] * r2[1] - n2[1] * r2[0]};
+        double w[3];
+        for (int a = 0; a < 3; ++a) w[a] = (d[a] + A2 * r2[a]) - A1 * r1[a];
+        double wt1 = w[0] * t1[0] + w[1] * t1[1] + w[2] * t1[2];
+        double wt2 = w[0] * t2[0] + w[1] * t2[1] + w[2] * t2[2];
+        double wr1 = w[0] * r1[0] + w[1] * r1[1] + w[2] * r1[2];
+        double wr2 = w[0] * r2[0] + w[1] * r2[1] + w[2] * r2[2];
+        double tt = t1[0] * t2[0] + t1[1] * t2[1] + t1[2] * t2[2];
+        /* half the gradient and Hessian of |w|^2 in the two rim angles */
+        double g1 = -(A1 * wt1), g2 = A2 * wt2;
+        double h11 = A1 * A1 + A1 * wr1, h22 = A2 * A2 - A2 * wr2, h12 = -(A1 * A2 * tt);
+        double det = h11 * h22 - h12 * h12;
+        if (!(h11 > 0.0 && det > 0.0)) return -1;
+        double s1 = -(h22 * g1 - h12 * g2) / det;
+        double s2 = -(h11 * g2 - h12 * g1) / det;
+        for (int a = 0; a < 3; ++a) {
+            r1[a] = r1[a] + s1 * t1[a];
+            r2[a] = r2[a] + s2 * t2[a];
+        }
+        o_sd_unit(r1);
+        o_sd_unit(r2);
+        double p[3], q[3];
+        for (int a = 0; a < 3; ++a) {
+            p[a] = A1 * r1[a];
+            q[a] = d[a] + A2 * r2[a];
+        }
+        int c = o_sd_certify(p, q, d, n1, A1, n2, A2, T);
+        if (c >= 0) return c;
+    }
+    return -1;
+}
+
+/* Is the minimum distance between core disk 1 (centre 0, n1, A1) and core
+ * disk 2 (centre d, n2, A2) at most T (T >= 0)? */
+int o_sd_within(const double d[3], const double n1[3], double A1, const double n2[3], double A2,
+                double T)
+{
+    double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double R = (A1 + A2) + T;
+    if (dd > R * R) return 0;
+    if (o_disks_meet(d, n1, A1, n2, A2)) return 1;
+    /* separating directions: the centre line and both normals */
+    double u[3];
+    if (dd > 0.0) {
+        double r = sqrt(dd);
+        u[0] = d[0] / r;
+        u[1] = d[1] / r;
+        u[2] = d[2] / r;
+        if (o_sd_lower(u, d, n1, A1, n2, A2) > T) return 0;
+    }
+    double h1 = n1[0] * d[0] + n1[1] * d[1] + n1[2] * d[2];
+    double h2 = n2[0] * d[0] + n2[1] * d[1] + n2[2] * d[2];
+    for (int a = 0; a < 3; ++a) u[a] = (h1 >= 0.0) ? n1[a] : -n1[a];
+    if (o_sd_lower(u, d, n1, A1, n2, A2) > T) return 0;
+    for (int a = 0; a < 3; ++a) u[a] = (h2 >= 0.0) ? n2[a] : -n2[a];
+    if (o_sd_lower(u, d, n1, A1, n2, A2) > T) return 0;
+    /* the point of each rim nearest the other disk's plane; where its
+     * projection leaves the other disk, the pair starts a Newton run */
+    double st1[2][3], st2[2][3];
+    int ns = 0;
+    double c12 = n2[0] * n1[0] + n2[1] * n1[1] + n2[2] * n1[2];
+    double m[3] = {n2[0] - c12 * n1[0], n2[1] - c12 * n1[1], n2[2] - c12 * n1[2]};
+    double mm = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+    if (mm > 0.0) {
+        double r = sqrt(mm), p[3], x[3], y[3], q[3];
+        for (int a = 0; a < 3; ++a) {
+            double e = m[a] / r;
+            p[a] = (h2 >= 0.0) ? A1 * e : -(A1 * e);
+            x[a] = p[a] - d[a];
+        }
+        int rim = o_sd_proj(x, n2, A2, y);
+        for (int a = 0; a < 3; ++a) q[a] = d[a] + y[a];
+        int c = o_sd_certify(p, q, d, n1, A1, n2, A2, T);
+        if (c >= 0) return c;
+        if (rim) {
+            for (int a = 0; a < 3; ++a) {
+                st1[ns][a] = p[a];
+                st2[ns][a] = y[a];
+            }
+            o_sd_unit(st1[ns]);
+            o_sd_unit(st2[ns]);
+            ++ns;
+        }
+    }
+    double c21 = n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2];
+    m[0] = n1[0] - c21 * n2[0];
+    m[1] = n1[1] - c21 * n2[1];
+    m[2] = n1[2] - c21 * n2[2];
+    mm = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+    if (mm > 0.0) {
+        double r = sqrt(mm), y[3], q[3], p[3];
+        for (int a = 0; a < 3; ++a) {
+            double e = m[a] / r;
+            y[a] = (h1 >= 0.0) ? -(A2 * e) : A2 * e;
+            q[a] = d[a] + y[a];
+        }
+        int rim = o_sd_proj(q, n1, A1, p);
+        int c = o_sd_certify(p, q, d, n1, A1, n2, A2, T);
+        if (c >= 0) return c;
+        if (rim) {
+            for (int a = 0; a < 3; ++a) {
+                st1[ns][a] = p[a];
+                st2[ns][a] = y[a];
+            }
+            o_sd_unit(st1[ns]);
+            o_sd_unit(st2[ns]);
+            ++ns;
+        }
+    }
+    /* alternating projections from the point of disk 1 nearest disk 2's
+     * centre; after six rounds, Newton from the current pair and from the
+     * rim starts above */
+    double p[3], q[3], x[3], y[3];
+    o_sd_proj(d, n1, A1, p);
+    for (int k = 1; k <= 64; ++k) {
+        for (int a = 0; a < 3; ++a) x[a] = p[a] - d[a];
+        o_sd_proj(x, n2, A2, y);
+        for (int a = 0; a < 3; ++a) q[a] = d[a] + y[a];
+        o_sd_proj(q, n1, A1, p);
+        int c = o_sd_certify(p, q, d, n1, A1, n2, A2, T);
+        if (c >= 0) return c;
+        if (k == 6) {
+            double pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+            double yy = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+            if (pp > 0.0 && yy > 0.0) {
+                double r1[3] = {p[0], p[1], p[2]}, r2[3] = {y[0], y[1], y[2]};
+                o_sd_unit(r1);
+                o_sd_unit(r2);
+                c = o_sd_newton(d, n1, A1, n2, A2, T, r1, r2);
+                if (c >= 0) return c;
+            }
+            for (int j = 0; j < ns; ++j) {
+                c = o_sd_newton(d, n1, A1, n2, A2, T, st1[j], st2[j]);
+                if (c >= 0) return c;
+            }
+        }
+    }
+    return 1;
+}
+
+/* Spherodisks at c1 and c2 (outer radii a1, a2; half-thicknesses
+ * h = thick_ratio * a): do they overlap?  Lower particle id as disk 1. */
+int o_spherodisks_overlap(const double c1[3], const double n1[3], double a1,
+                          const double c2[3], const double n2[3], double a2,
+                          double thick_ratio, double gap, const double box[3])
+{
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = o_minimg(c2[a] - c1[a], box[a]);
+    double h1 = thick_ratio * a1, h2 = thick_ratio * a2;
+    return o_sd_within(d, n1, a1 - h1, n2, a2 - h2, (h1 + h2) + gap);
 }
 
 /* ------------------------------------------------------------------ */
@@ -352,6 +607,11 @@ static int o_contact(const o_state *st, int64_t i, const double y[3], const doub
         return (i < j) ? o_disks_intersect(y, ny, Ri, xj, nj, Rj, p->box)
                        : o_disks_intersect(xj, nj, Rj, y, ny, Ri, p->box);
     }
+    if (p->shape == O_SPHERODISK) {
+        const double *nj = &st->nrm[3 * j];
+        return (i < j) ? o_spherodisks_overlap(y, ny, Ri, xj, nj, Rj, p->thick_ratio, 0.0, p->box)
+                       : o_spherodisks_overlap(xj, nj, Rj, y, ny, Ri, p->thick_ratio, 0.0, p->box);
+    }
     double d0 = o_minimg(y[0] - xj[0], p->box[0]);
     double d1 = o_minimg(y[1] - xj[1], p->box[1]);
     double q = d0 * d0 + d1 * d1;
@@ -436,7 +696,7 @@ static void o_trial(const o_state *st, int64_t i, const double old[3], const dou
         if (a < p->dim) y[a] = o_wrap(old[a] + v[a], p->box[a]);
         else y[a] = old[a];
     }
-    if (p->shape == O_PLATELET) {
+    if (p->shape == O_PLATELET || p->shape == O_SPHERODISK) {
         double w[3];
         o_unitvec(3, p->seed, (uint64_t)i, (uint64_t)st->t, kind, k, l, 1, p->c_n, w);
         double m0 = nold[0] + w[0], m1 = nold[1] + w[1], m2 = nold[2] + w[2];
@@ -735,7 +995,9 @@ static double o_pair_q(const o_state *st, int64_t i, int64_t j)
 }
 
 /* Pairs i<j whose shapes, grown by `gap` ((R_i + R_j) + gap for balls; radii
- * a + gap/2 for platelets), overlap or touch; written sorted by (i, j).
+ * a + gap/2 for zero-thickness platelets; core-disk distance at most
+ * h_i + h_j + gap for spherodisks, i.e. shells of thickness gap/2 around
+ * each surface), overlap or touch; written sorted by (i, j).
  * Returns the total count (which may exceed cap; only cap pairs written). */
 int64_t o_pairs_brute(const o_state *st, double s, double gap, int64_t cap, int32_t *ij)
 {
@@ -748,6 +1010,10 @@ int64_t o_pairs_brute(const o_state *st, double s, double gap, int64_t cap, int3
                 double ai = o_radius(st, s, i) + 0.5 * gap, aj = o_radius(st, s, j) + 0.5 * gap;
                 hit = o_disks_intersect(&st->pos[3 * i], &st->nrm[3 * i], ai,
                                         &st->pos[3 * j], &st->nrm[3 * j], aj, p->box);
+            } else if (p->shape == O_SPHERODISK) {
+                hit = o_spherodisks_overlap(&st->pos[3 * i], &st->nrm[3 * i], o_radius(st, s, i),
+                                            &st->pos[3 * j], &st->nrm[3 * j], o_radius(st, s, j),
+                                            p->thick_ratio, gap, p->box);
             } else {
                 double sig = (o_radius(st, s, i) + o_radius(st, s, j)) + gap;
                 hit = o_pair_q(st, i, j) <= sig * sig;
@@ -813,6 +1079,10 @@ int o_percolation(const o_state *st, double s, double gap, int32_t *mask)
                 double ai = o_radius(st, s, i) + 0.5 * gap, aj = o_radius(st, s, j) + 0.5 * gap;
                 hit = o_disks_intersect(&st->pos[3 * i], &st->nrm[3 * i], ai,
                                         &st->pos[3 * j], &st->nrm[3 * j], aj, p->box);
+            } else if (p->shape == O_SPHERODISK) {
+                hit = o_spherodisks_overlap(&st->pos[3 * i], &st->nrm[3 * i], o_radius(st, s, i),
+                                            &st->pos[3 * j], &st->nrm[3 * j], o_radius(st, s, j),
+                                            p->thick_ratio, gap, p->box);
             } else {
                 double sig = (o_radius(st, s, i) + o_radius(st, s, j)) + gap;
                 hit = o_pair_q(st, i, j) <= sig * sig;

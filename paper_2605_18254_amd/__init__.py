@@ -15,11 +15,12 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["SRM", "SrmError", "rsa", "lib", "LIB_PATH", "BALL", "PLATELET", "MAIN", "SHAKE"]
+__all__ = ["SRM", "SrmError", "rsa", "lib", "LIB_PATH", "BALL", "PLATELET", "SPHERODISK",
+           "MAIN", "SHAKE"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libsrm.so")
 
-BALL, PLATELET = 0, 1
+BALL, PLATELET, SPHERODISK = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 MAIN, SHAKE = 0, 1
 OK, EINVAL, ENOMEM, EDEVICE, EOVERLAP, ENOTCONV, ECAPACITY = 0, -1, -2, -3, -4, -5, -6
@@ -231,7 +232,7 @@ class SRM:
         p.n_k, p.n_l, p.seed = int(n_k), int(n_l), int(seed)
         self.params = p
         self.dim, self.n = int(dim), int(n)
-        self.plate = int(shape) == PLATELET
+        self.plate = int(shape) in (PLATELET, SPHERODISK)
         device = _is_torch(pos)
         self.mem_kind = MEM_DEVICE if device else MEM_HOST
         if device:

@@ -698,8 +698,9 @@ __global__ void __launch_bounds__(kBlock) k_check_ball(PassArgs a, int32_t check
 // Thin platelets (3D): the trial moves the centre by c_m times a random
 // unit vector (stream 0) and the normal to (n + c_n w) / |n + c_n w| (w a
 // random unit vector, stream 1); both are accepted or rejected together.
-// The pair test is the exact disk-disk intersection with the lower id as
-// disk 1.
+// The pair test is the exact disk-disk intersection (zero thickness) or
+// the spherodisk test (platelets_touch), with the lower id as disk 1.
+template <bool SD>
 __device__ __forceinline__ bool platelet_hits(const PassArgs &a, const int32_t *lo,
                                               const int32_t *hi, int32_t self, int32_t self_id,
                                               double yx, double yy, double yz, const double ny[3],
@@ -720,12 +721,12 @@ __device__ __forceinline__ bool platelet_hits(const PassArgs &a, const int32_t *
                 const double dx = min_image(X[q] - yx, a.g.box[0], a.g.half[0]);
                 const double dy = min_image(Y[q] - yy, a.g.box[1], a.g.half[1]);
                 const double dz = min_image(Z[q] - yz, a.g.box[2], a.g.half[2]);
-                hit = disks_intersect(dx, dy, dz, ny, ai, nq, aj);
+                hit = platelets_touch<SD>(dx, dy, dz, ny, ai, nq, aj, a.tau);
             } else {
                 const double dx = min_image(yx - X[q], a.g.box[0], a.g.half[0]);
                 const double dy = min_image(yy - Y[q], a.g.box[1], a.g.half[1]);
                 const double dz = min_image(yz - Z[q], a.g.box[2], a.g.half[2]);
-                hit = disks_intersect(dx, dy, dz, nq, aj, ny, ai);
+                hit = platelets_touch<SD>(dx, dy, dz, nq, aj, ny, ai, a.tau);
             }
             if (hit) return true;
         }
@@ -733,6 +734,7 @@ __device__ __forceinline__ bool platelet_hits(const PassArgs &a, const int32_t *
     return false;
 }
 
+template <bool SD>
 __device__ void migrate_platelet_cell(const PassArgs &a, int32_t cx, int32_t cy, int32_t cz);
 
 // Platelets on crowded grids: one 64-lane wavefront per colour cell, the
@@ -784,6 +786,7 @@ __device__ __forceinline__ void plate_trial(const PassArgs &a, const PlateOwn &m
 }
 
 // The exact pair test of platelet_hits for one candidate.
+template <bool SD>
 __device__ __forceinline__ bool plate_pair_hit(const PassArgs &a, int32_t self_id, const double y[3],
                                                const double ny[3], double ai, double qx, double qy,
                                                double qz, const double nq[3], double aj,
@@ -793,15 +796,15 @@ __device__ __forceinline__ bool plate_pair_hit(const PassArgs &a, int32_t self_i
         const double dx = min_image(qx - y[0], a.g.box[0], a.g.half[0]);
         const double dy = min_image(qy - y[1], a.g.box[1], a.g.half[1]);
         const double dz = min_image(qz - y[2], a.g.box[2], a.g.half[2]);
-        return disks_intersect(dx, dy, dz, ny, ai, nq, aj);
+        return platelets_touch<SD>(dx, dy, dz, ny, ai, nq, aj, a.tau);
     }
     const double dx = min_image(y[0] - qx, a.g.box[0], a.g.half[0]);
     const double dy = min_image(y[1] - qy, a.g.box[1], a.g.half[1]);
     const double dz = min_image(y[2] - qz, a.g.box[2], a.g.half[2]);
-    return disks_intersect(dx, dy, dz, nq, aj, ny, ai);
+    return platelets_touch<SD>(dx, dy, dz, nq, aj, ny, ai, a.tau);
 }
 
-template <class LDS>
+template <bool SD, class LDS>
 __device__ __forceinline__ bool plate_ref_hit(const PassArgs &a, const LDS &L, int32_t ref,
                                               int32_t self_id, const double y[3],
                                               const double ny[3], double ai)
@@ -809,15 +812,16 @@ __device__ __forceinline__ bool plate_ref_hit(const PassArgs &a, const LDS &L, i
     if (ref < 0) {
         const PlateOwn o = L.own[-ref - 1];
         const double nq[3] = {o.n0, o.n1, o.n2};
-        return plate_pair_hit(a, self_id, y, ny, ai, o.x, o.y, o.z, nq, o.a, o.id);
+        return plate_pair_hit<SD>(a, self_id, y, ny, ai, o.x, o.y, o.z, nq, o.a, o.id);
     }
     const double nq[3] = {a.buf.nrm[0][ref], a.buf.nrm[1][ref], a.buf.nrm[2][ref]};
     const double aj = a.buf.rho ? a.s * a.buf.rho[ref] : a.s;
-    return plate_pair_hit(a, self_id, y, ny, ai, a.buf.x[0][ref], a.buf.x[1][ref],
+    return plate_pair_hit<SD>(a, self_id, y, ny, ai, a.buf.x[0][ref], a.buf.x[1][ref],
                           a.buf.x[2][ref], nq, aj, a.buf.id[ref]);
 }
 
 // Algorithm 3 for the platelets of one cell (global-memory path, one thread).
+template <bool SD>
 __device__ void migrate_platelet_cell(const PassArgs &a, int32_t cx, int32_t cy, int32_t cz)
 {
     const int32_t c = cx + a.g.na[0] * (cy + a.g.na[1] * cz);
@@ -847,7 +851,7 @@ __device__ void migrate_platelet_cell(const PassArgs &a, int32_t cx, int32_t cy,
             const double mm = m0 * m0 + m1 * m1 + m2 * m2;
             const double inv = 1.0 / __builtin_sqrt(mm);
             const double ny[3] = {m0 * inv, m1 * inv, m2 * inv};
-            if (!platelet_hits(a, lo, hi, p, pid, yx, yy, yz, ny, ai)) {
+            if (!platelet_hits<SD>(a, lo, hi, p, pid, yx, yy, yz, ny, ai)) {
                 X[p] = yx;
                 Y[p] = yy;
                 Z[p] = yz;
@@ -863,7 +867,7 @@ __device__ void migrate_platelet_cell(const PassArgs &a, int32_t cx, int32_t cy,
     }
 }
 
-template <int NEAR>
+template <int NEAR, bool SD>
 __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, ColourLattice L)
 {
     __shared__ PlateLds<NEAR> S;
@@ -881,7 +885,7 @@ __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, Colour
     const int32_t cnt = end - beg;
     if (cnt == 0) return;
     if (cnt > kPlateOwn) {
-        if (lane == 0) migrate_platelet_cell(a, cx, cy, cz);
+        if (lane == 0) migrate_platelet_cell<SD>(a, cx, cy, cz);
         return;
     }
     int32_t lo[Rows<3>::kRanges], hi[Rows<3>::kRanges];
@@ -972,7 +976,7 @@ __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, Colour
                 double y[3], ny[3];
                 plate_trial(a, me, active ? l : l0, y, ny);
                 const bool hit = active && m > 0 &&
-                                 plate_ref_hit(a, S, S.near[k * NEAR + j], me.id, y, ny, me.a);
+                                 plate_ref_hit<SD>(a, S, S.near[k * NEAR + j], me.id, y, ny, me.a);
                 const unsigned long long hits = __ballot(hit);
                 int32_t win = -1;
                 for (int32_t gg = 0; gg < G && l0 + gg <= a.n_l; ++gg) {
@@ -998,7 +1002,7 @@ __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, Colour
                 plate_trial(a, me, l, y, ny);
                 bool hit = false;
                 for (int32_t e = lane; e < m; e += 64)
-                    hit = hit || plate_ref_hit(a, S, S.near[k * NEAR + e], me.id, y, ny, me.a);
+                    hit = hit || plate_ref_hit<SD>(a, S, S.near[k * NEAR + e], me.id, y, ny, me.a);
                 if (__ballot(hit) == 0) {
                     code = l;
                     w0 = y[0];
@@ -1019,11 +1023,11 @@ __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, Colour
                 for (int r = 0; r < Rows<3>::kRanges; ++r) {
                     for (int32_t q = lo[r] + lane; q < hi[r]; q += 64) {
                         if (q >= beg && q < end) continue;
-                        hit = hit || plate_ref_hit(a, S, q, me.id, y, ny, me.a);
+                        hit = hit || plate_ref_hit<SD>(a, S, q, me.id, y, ny, me.a);
                     }
                 }
                 for (int32_t j = lane; j < cnt; j += 64)
-                    if (j != k) hit = hit || plate_ref_hit(a, S, -(j + 1), me.id, y, ny, me.a);
+                    if (j != k) hit = hit || plate_ref_hit<SD>(a, S, -(j + 1), me.id, y, ny, me.a);
                 if (__ballot(hit) == 0) {
                     code = l;
                     w0 = y[0];
@@ -1071,6 +1075,7 @@ __global__ void __launch_bounds__(64) k_migrate_platelet_wave(PassArgs a, Colour
     }
 }
 
+template <bool SD>
 __device__ __forceinline__ bool check_platelet_one(const PassArgs &a, int32_t p)
 {
     const double x = a.buf.x[0][p], y = a.buf.x[1][p], z = a.buf.x[2][p];
@@ -1081,9 +1086,10 @@ __device__ __forceinline__ bool check_platelet_one(const PassArgs &a, int32_t p)
     int32_t lo[Rows<3>::kRanges], hi[Rows<3>::kRanges];
     stencil_slices<3>(a.g, a.start, cx, cy, cz, lo, hi);
     const double ai = a.buf.rho ? a.s * a.buf.rho[p] : a.s;
-    return platelet_hits(a, lo, hi, p, a.buf.id[p], x, y, z, np_, ai);
+    return platelet_hits<SD>(a, lo, hi, p, a.buf.id[p], x, y, z, np_, ai);
 }
 
+template <bool SD>
 __global__ void __launch_bounds__(kBlock) k_check_platelet(PassArgs a, int32_t check_all,
                                                            Counters *cnt)
 {
@@ -1091,7 +1097,7 @@ __global__ void __launch_bounds__(kBlock) k_check_platelet(PassArgs a, int32_t c
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += gridDim.x * blockDim.x) {
         const int32_t p = check_all ? i : a.failed[1 + i];
-        if (check_platelet_one(a, p)) atomicOr(&cnt->overlap, 1);
+        if (check_platelet_one<SD>(a, p)) atomicOr(&cnt->overlap, 1);
     }
 }
 
@@ -1239,10 +1245,14 @@ hipError_t migrate_colour(int dim, int shape, bool poly, const PassArgs &a, int 
         const double reach = 2.0 * a.s + 2.0 * a.c_m;
         const double vol = a.g.box[0] * a.g.box[1] * a.g.box[2];
         const double expect = (double)a.n / vol * (4.0 / 3.0) * 3.141592653589793 * reach * reach * reach;
-        if (expect > 20.0)
-            hipLaunchKernelGGL((k_migrate_platelet_wave<kPlateNearLong>), grid, block, 0, stream, a, L);
-        else
-            hipLaunchKernelGGL((k_migrate_platelet_wave<kPlateNearShort>), grid, block, 0, stream, a, L);
+        const bool sd = a.tau != 0.0;  // spherodisks
+        if (expect > 20.0) {
+            if (sd) hipLaunchKernelGGL((k_migrate_platelet_wave<kPlateNearLong, true>), grid, block, 0, stream, a, L);
+            else hipLaunchKernelGGL((k_migrate_platelet_wave<kPlateNearLong, false>), grid, block, 0, stream, a, L);
+        } else {
+            if (sd) hipLaunchKernelGGL((k_migrate_platelet_wave<kPlateNearShort, true>), grid, block, 0, stream, a, L);
+            else hipLaunchKernelGGL((k_migrate_platelet_wave<kPlateNearShort, false>), grid, block, 0, stream, a, L);
+        }
         main_done(SRM_KERNEL_PLATELET | SRM_KERNEL_WAVE);
     } else if (dim == 3) {
         if (poly) hipLaunchKernelGGL((k_migrate_wave<3, true>), grid, block, 0, stream, a, L);
@@ -1277,7 +1287,8 @@ hipError_t check_overlaps(int dim, int shape, bool poly, const PassArgs &a, bool
     const dim3 grid(check_all ? nb : (nb < 1024 ? nb : 1024)), block(kBlock);
     const int32_t all = check_all ? 1 : 0;
     if (shape == SRM_PLATELET) {
-        hipLaunchKernelGGL(k_check_platelet, grid, block, 0, stream, a, all, cnt);
+        if (a.tau != 0.0) hipLaunchKernelGGL(k_check_platelet<true>, grid, block, 0, stream, a, all, cnt);
+        else hipLaunchKernelGGL(k_check_platelet<false>, grid, block, 0, stream, a, all, cnt);
     } else if (dim == 3) {
         if (poly) hipLaunchKernelGGL((k_check_ball<3, true>), grid, block, 0, stream, a, all, cnt);
         else hipLaunchKernelGGL((k_check_ball<3, false>), grid, block, 0, stream, a, all, cnt);

@@ -23,6 +23,7 @@ struct PairArgs {
     Grid g;
     int32_t n;
     int32_t shape;
+    double tau;        // spherodisks: half-thickness / outer radius (0: zero-thickness disks)
     double s;          // radius scale
     double gap;
 };
@@ -40,7 +41,11 @@ __device__ __forceinline__ bool pair_hit(const PairArgs &a, int32_t p, int32_t q
         const double ez = min_image(a.buf.x[2][q] - a.buf.x[2][p], a.g.box[2], a.g.half[2]);
         const double n1[3] = {a.buf.nrm[0][p], a.buf.nrm[1][p], a.buf.nrm[2][p]};
         const double n2[3] = {a.buf.nrm[0][q], a.buf.nrm[1][q], a.buf.nrm[2][q]};
-        return disks_intersect(ex, ey, ez, n1, Rp + 0.5 * a.gap, n2, Rq + 0.5 * a.gap);
+        // zero thickness: radii grown by gap / 2 in their planes; spherodisks:
+        // shells grown by gap / 2 around each surface
+        if (a.tau == 0.0)
+            return disks_intersect(ex, ey, ez, n1, Rp + 0.5 * a.gap, n2, Rq + 0.5 * a.gap);
+        return spherodisks_overlap(ex, ey, ez, n1, Rp, n2, Rq, a.tau, a.gap);
     }
     const double dx = min_image(a.buf.x[0][p] - a.buf.x[0][q], a.g.box[0], a.g.half[0]);
     const double dy = min_image(a.buf.x[1][p] - a.buf.x[1][q], a.g.box[1], a.g.half[1]);
@@ -221,10 +226,11 @@ __global__ void __launch_bounds__(kBlock) k_nearest(PairArgs a, double r2, doubl
 }  // namespace
 
 hipError_t pairs_count(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
-                       int shape, double s, double gap, int32_t *rowcnt, hipStream_t stream)
+                       int shape, double tau, double s, double gap, int32_t *rowcnt,
+                       hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
-    const PairArgs a{b, start, g, n, shape, s, gap};
+    const PairArgs a{b, start, g, n, shape, tau, s, gap};
     if (dim == 3)
         hipLaunchKernelGGL((k_pairs<3, false>), dim3(blocks_for(n)), dim3(kBlock), 0, stream, a,
                            rowcnt, nullptr, nullptr);
@@ -235,11 +241,11 @@ hipError_t pairs_count(int dim, const PBuf &b, const int32_t *start, const Grid 
 }
 
 hipError_t pairs_emit(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
-                      int shape, double s, double gap, const int32_t *rowoff, int32_t *partner,
-                      int32_t *ij, hipStream_t stream)
+                      int shape, double tau, double s, double gap, const int32_t *rowoff,
+                      int32_t *partner, int32_t *ij, hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
-    const PairArgs a{b, start, g, n, shape, s, gap};
+    const PairArgs a{b, start, g, n, shape, tau, s, gap};
     if (dim == 3)
         hipLaunchKernelGGL((k_pairs<3, true>), dim3(blocks_for(n)), dim3(kBlock), 0, stream, a,
                            nullptr, rowoff, partner);

@@ -54,7 +54,9 @@ struct srm_ctx {
     hipStream_t stream = nullptr;
     int32_t n = 0;
     int dim = 2;
-    bool poly = false, plate = false;
+    bool poly = false, plate = false;  // plate: zero-thickness disks or spherodisks
+    int kshape = SRM_BALL;             // kernel family: SRM_BALL or SRM_PLATELET
+    double tau = 0.0;                  // spherodisks: half-thickness / outer radius
     double rho_max = 1.0;
     double sum_rho_d = 0.0;  // sum of rho_i^dim (fraction)
     double s = 0.0;
@@ -169,16 +171,27 @@ Grid make_grid(const srm_ctx *c, double rmax)
     return sweep_grid(c->dim, c->p.box, c->ncap, c->p.c_m, rmax);
 }
 
+// Volume per cubed radius scale of one particle with shape radius 1: ball
+// omega_d; thin platelet pi a^2 t with t = thick_ratio 2a (cylinder);
+// spherodisk 2 pi A^2 h + pi^2 A h^2 + 4/3 pi h^3 (core radius A = 1 - h,
+// half-thickness h = thick_ratio; Steiner's formula).
+double volume_coeff(const srm_ctx *c)
+{
+    if (c->p.shape == SRM_SPHERODISK) {
+        const double h = c->p.thick_ratio, A = 1.0 - h;
+        return 2.0 * M_PI * A * A * h + M_PI * M_PI * A * h * h + 4.0 / 3.0 * M_PI * h * h * h;
+    }
+    if (c->plate) return 2.0 * M_PI * c->p.thick_ratio;  // pi a^2 (thick_ratio 2a)
+    return (c->dim == 2) ? M_PI : 4.0 * M_PI / 3.0;
+}
+
 double fraction_at(const srm_ctx *c, double s)
 {
     double vbox = 1.0;
     for (int a = 0; a < c->dim; ++a) vbox *= c->p.box[a];
     double sd = 1.0;
     for (int a = 0; a < c->dim; ++a) sd *= s;
-    double coeff;
-    if (c->plate) coeff = 2.0 * M_PI * c->p.thick_ratio;  // pi a^2 (thick_ratio 2a)
-    else coeff = (c->dim == 2) ? M_PI : 4.0 * M_PI / 3.0;
-    return coeff * sd * c->sum_rho_d / vbox;
+    return volume_coeff(c) * sd * c->sum_rho_d / vbox;
 }
 
 // Sec. 2 step a: s' = min(s + c_w * s_target, clamp), the clamp being
@@ -195,10 +208,7 @@ double scale_for_fraction(const srm_ctx *c, double f)
 {
     double vbox = 1.0;
     for (int a = 0; a < c->dim; ++a) vbox *= c->p.box[a];
-    double coeff;
-    if (c->plate) coeff = 2.0 * M_PI * c->p.thick_ratio;
-    else coeff = (c->dim == 2) ? M_PI : 4.0 * M_PI / 3.0;
-    const double sd = f * vbox / (coeff * c->sum_rho_d);
+    const double sd = f * vbox / (volume_coeff(c) * c->sum_rho_d);
     return (c->dim == 2) ? sqrt(sd) : cbrt(sd);
 }
 
@@ -242,6 +252,7 @@ PassArgs pass_args(srm_ctx *c, const PBuf &b, const Grid &g, double s, int kind,
     a.n_l = c->p.n_l;
     a.c_m = c->p.c_m;
     a.c_n = c->p.c_n;
+    a.tau = (c->p.shape == SRM_SPHERODISK) ? c->p.thick_ratio : 0.0;
     a.ovf = c->ovf;
     a.ovf_max_tiles = c->ovf_max_tiles;
     a.failed = c->failed;
@@ -263,7 +274,7 @@ srm_status run_pass(srm_ctx *c, const PBuf &b, const Grid &g, double s, int kind
         // m0 .. m1 brackets the colour phase's main kernel alone
         hipEvent_t m0 = c->mark();
         hipEvent_t m1 = c->prof_on ? c->event() : nullptr;
-        HIP_TRY(migrate_colour(c->dim, c->p.shape, c->poly, a, colour, c->stream, &launched, m1,
+        HIP_TRY(migrate_colour(c->dim, c->kshape, c->poly, a, colour, c->stream, &launched, m1,
                                &which));
         if (launched) {
             hipEvent_t e1 = c->mark();
@@ -287,7 +298,7 @@ srm_status run_pass(srm_ctx *c, const PBuf &b, const Grid &g, double s, int kind
     if (!want_check) return SRM_OK;
     HIP_TRY(launch_zero_counters(c->dcnt, c->stream));
     hipEvent_t e2 = c->mark();
-    HIP_TRY(check_overlaps(c->dim, c->p.shape, c->poly, a, false, c->dcnt, c->stream));
+    HIP_TRY(check_overlaps(c->dim, c->kshape, c->poly, a, false, c->dcnt, c->stream));
     c->span(2, e2, c->mark());
     if (c->prof_on) c->prof.checks += 1;
     HIP_TRY(hipMemcpyAsync(c->hcnt, c->dcnt, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
@@ -304,8 +315,11 @@ srm_status check_params(const srm_params *p)
 {
     if (!p) return fail(SRM_EINVAL, "params is NULL");
     if (p->dim != 2 && p->dim != 3) return fail(SRM_EINVAL, "dim must be 2 or 3");
-    if (p->shape != SRM_BALL && p->shape != SRM_PLATELET) return fail(SRM_EINVAL, "bad shape");
-    if (p->shape == SRM_PLATELET && p->dim != 3) return fail(SRM_EINVAL, "platelets are 3D");
+    if (p->shape != SRM_BALL && p->shape != SRM_PLATELET && p->shape != SRM_SPHERODISK)
+        return fail(SRM_EINVAL, "bad shape");
+    if (p->shape != SRM_BALL && p->dim != 3) return fail(SRM_EINVAL, "platelets are 3D");
+    if (p->shape == SRM_SPHERODISK && !(p->thick_ratio > 0.0 && p->thick_ratio < 0.5))
+        return fail(SRM_EINVAL, "spherodisks need 0 < thick_ratio < 0.5");
     if (p->n < 1 || p->n > 0x7fffffffLL) return fail(SRM_EINVAL, "n out of range");
     for (int a = 0; a < p->dim; ++a)
         if (!(p->box[a] > 0.0) || !isfinite(p->box[a])) return fail(SRM_EINVAL, "box edge <= 0");
@@ -333,7 +347,7 @@ srm_status srm_init(const srm_params *p, const double *pos, const double *rho,
     if (!pos || !out) return fail(SRM_EINVAL, "pos and out must not be NULL");
     if (mem_kind != SRM_MEM_HOST && mem_kind != SRM_MEM_DEVICE)
         return fail(SRM_EINVAL, "bad mem_kind");
-    if (p->shape == SRM_PLATELET && !normals) return fail(SRM_EINVAL, "platelets need normals");
+    if (p->shape != SRM_BALL && !normals) return fail(SRM_EINVAL, "platelets need normals");
     if (!(s0 >= 0.0) || !isfinite(s0)) return fail(SRM_EINVAL, "bad s0");
     if (sweep0 < 0 || sweep0 > 0xffffffffLL) return fail(SRM_EINVAL, "sweep0 out of range");
 
@@ -343,7 +357,9 @@ srm_status srm_init(const srm_params *p, const double *pos, const double *rho,
     if (c->p.dim == 2) c->p.box[2] = 1.0;
     c->n = (int32_t)p->n;
     c->dim = p->dim;
-    c->plate = p->shape == SRM_PLATELET;
+    c->plate = p->shape != SRM_BALL;
+    c->kshape = c->plate ? SRM_PLATELET : SRM_BALL;
+    c->tau = (p->shape == SRM_SPHERODISK) ? p->thick_ratio : 0.0;
     c->poly = rho != nullptr;
     c->s = s0;
     c->s_stop = p->s_target;
@@ -437,7 +453,7 @@ srm_status srm_init(const srm_params *p, const double *pos, const double *rho,
         return bail(fail(SRM_EDEVICE, "initial binning failed"));
     if (c->hcnt->bad) return bail(fail(SRM_EINVAL, "a coordinate is outside [0, L) or NaN"));
     PassArgs a = pass_args(c, c->P, g, c->s, 0, 0);
-    if (check_overlaps(c->dim, c->p.shape, c->poly, a, true, c->dcnt, c->stream) != hipSuccess ||
+    if (check_overlaps(c->dim, c->kshape, c->poly, a, true, c->dcnt, c->stream) != hipSuccess ||
         hipMemcpyAsync(c->hcnt, c->dcnt, sizeof(Counters), hipMemcpyDeviceToHost, c->stream) ||
         hipStreamSynchronize(c->stream))
         return bail(fail(SRM_EDEVICE, "initial check failed"));
@@ -751,7 +767,7 @@ srm_status srm_pairs(srm_ctx *c, double gap, int64_t cap, int32_t *ij, int64_t *
     const double reach = 2.0 * (c->s * c->rho_max) + gap;
     const Grid g = cutoff_grid(c, reach);
     if ((st = bin(c, c->P, c->T, g))) return st;
-    HIP_TRY(pairs_count(c->dim, c->T, c->sc.start, g, c->n, c->p.shape, c->s, gap, c->rowcnt,
+    HIP_TRY(pairs_count(c->dim, c->T, c->sc.start, g, c->n, c->kshape, c->tau, c->s, gap, c->rowcnt,
                         c->stream));
     int64_t total = 0;
     st = pair_total(c, &total);
@@ -769,7 +785,7 @@ srm_status srm_pairs(srm_ctx *c, double gap, int64_t cap, int32_t *ij, int64_t *
         HIP_TRY(hipMalloc(&d.p[1], (size_t)total * 2 * sizeof(int32_t)));
         out = (int32_t *)d.p[1];
     }
-    HIP_TRY(pairs_emit(c->dim, c->T, c->sc.start, g, c->n, c->p.shape, c->s, gap, c->rowoff,
+    HIP_TRY(pairs_emit(c->dim, c->T, c->sc.start, g, c->n, c->kshape, c->tau, c->s, gap, c->rowoff,
                        (int32_t *)d.p[0], out, c->stream));
     if (mem_kind == SRM_MEM_HOST)
         HIP_TRY(hipMemcpyAsync(ij, out, (size_t)total * 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -825,7 +841,7 @@ srm_status percolation_mask(srm_ctx *c, double gap, int32_t *mask)
     const double reach = 2.0 * (c->s * c->rho_max) + gap;
     const Grid g = cutoff_grid(c, reach);
     if ((st = bin(c, c->P, c->T, g))) return st;
-    HIP_TRY(pairs_count(c->dim, c->T, c->sc.start, g, c->n, c->p.shape, c->s, gap, c->rowcnt,
+    HIP_TRY(pairs_count(c->dim, c->T, c->sc.start, g, c->n, c->kshape, c->tau, c->s, gap, c->rowcnt,
                         c->stream));
     int64_t total = 0;
     if ((st = pair_total(c, &total))) return st;
@@ -840,7 +856,7 @@ srm_status percolation_mask(srm_ctx *c, double gap, int32_t *mask)
     HIP_TRY(hipMalloc(&d.p[4], 4 * sizeof(int32_t)));
     int32_t *ij = (int32_t *)d.p[1], *shift = (int32_t *)d.p[2], *flags = (int32_t *)d.p[4];
     auto *state = (unsigned long long *)d.p[3];
-    HIP_TRY(pairs_emit(c->dim, c->T, c->sc.start, g, c->n, c->p.shape, c->s, gap, c->rowoff,
+    HIP_TRY(pairs_emit(c->dim, c->T, c->sc.start, g, c->n, c->kshape, c->tau, c->s, gap, c->rowoff,
                        (int32_t *)d.p[0], ij, c->stream));
     const double *xs[3] = {c->P.x[0], c->P.x[1], c->P.x[2]};
     HIP_TRY(to_id_order(xs, c->dim, c->P.id, c->n, c->dtmp, c->stream));

@@ -178,6 +178,252 @@ __device__ __forceinline__ bool disks_intersect(double dx, double dy, double dz,
     return D * D <= (4.0 * Ap) * Bp;
 }
 
+// ---- spherodisks (Sec. 3.3's platelet model) ----------------------------
+// A spherodisk of outer radius a and thickness t = 2h is the set of points
+// within h of a flat core disk of radius A = a - h.  Two overlap iff the
+// distance between their core disks is at most h1 + h2 (touching counts).
+// Core disk 1: centre 0, unit normal n1, radius A1; core disk 2: centre d.
+// The decision uses two certificates:
+//  - points p on disk 1 and q on disk 2 with |q - p| <= T prove overlap;
+//  - a unit direction u with L(u) = u.d - A1 |u x n1| - A2 |u x n2| > T
+//    proves separation (A |u x n| is a disk's half-extent along u), and
+//    L((q* - p*)/|q* - p*|) is the distance at the closest pair.
+// Candidate pairs come from the zero-thickness test, the point of each rim
+// nearest the other plane, alternating projections between the disks and
+// Newton's method on the two rim angles; a pair within 1e-12 (A1 + A2) of
+// T, or left undecided, counts as overlapping.  Every expression matches
+// the oracle's, operation for operation.
+__device__ __forceinline__ double sd_lower(const double u[3], const double d[3],
+                                           const double n1[3], double A1, const double n2[3],
+                                           double A2)
+{
+    const double x0 = u[1] * n1[2] - u[2] * n1[1];
+    const double x1 = u[2] * n1[0] - u[0] * n1[2];
+    const double x2 = u[0] * n1[1] - u[1] * n1[0];
+    const double y0 = u[1] * n2[2] - u[2] * n2[1];
+    const double y1 = u[2] * n2[0] - u[0] * n2[2];
+    const double y2 = u[0] * n2[1] - u[1] * n2[0];
+    const double e1 = __builtin_sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+    const double e2 = __builtin_sqrt(y0 * y0 + y1 * y1 + y2 * y2);
+    const double ud = u[0] * d[0] + u[1] * d[1] + u[2] * d[2];
+    return (ud - A1 * e1) - A2 * e2;
+}
+
+// Nearest point y of the disk (centre 0, unit normal n, radius A) to x;
+// true when it lies on the rim.
+__device__ __forceinline__ bool sd_proj(const double x[3], const double n[3], double A,
+                                        double y[3])
+{
+    const double h = x[0] * n[0] + x[1] * n[1] + x[2] * n[2];
+    y[0] = x[0] - h * n[0];
+    y[1] = x[1] - h * n[1];
+    y[2] = x[2] - h * n[2];
+    const double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+    if (r2 <= A * A) return false;
+    const double f = A / __builtin_sqrt(r2);
+    y[0] = y[0] * f;
+    y[1] = y[1] * f;
+    y[2] = y[2] * f;
+    return true;
+}
+
+// 1: overlap, 0: separated, -1: undecided by the pair (p, q).
+__device__ __forceinline__ int sd_certify(const double p[3], const double q[3], const double d[3],
+                                          const double n1[3], double A1, const double n2[3],
+                                          double A2, double T)
+{
+    const double w0 = q[0] - p[0], w1 = q[1] - p[1], w2 = q[2] - p[2];
+    const double ww = w0 * w0 + w1 * w1 + w2 * w2;
+    if (ww <= T * T) return 1;
+    const double ub = __builtin_sqrt(ww);
+    const double u[3] = {w0 / ub, w1 / ub, w2 / ub};
+    const double lb = sd_lower(u, d, n1, A1, n2, A2);
+    if (lb > T) return 0;
+    if (ub - lb <= 1e-12 * (A1 + A2)) return 1;
+    return -1;
+}
+
+__device__ __forceinline__ void sd_unit(double v[3])
+{
+    const double r = __builtin_sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] = v[0] / r;
+    v[1] = v[1] / r;
+    v[2] = v[2] / r;
+}
+
+// Newton's method on the squared distance between the rim points A1 r1 and
+// d + A2 r2, rotating r1, r2 by the solved angles (r + s t renormalised,
+// t = n x r); stops where the Hessian is not positive definite.
+__device__ __noinline__ int sd_newton(const double d[3], const double n1[3], double A1,
+                                      const double n2[3], double A2, double T,
+                                      const double r1_in[3], const double r2_in[3])
+{
+    double r1[3] = {r1_in[0], r1_in[1], r1_in[2]}, r2[3] = {r2_in[0], r2_in[1], r2_in[2]};
+    for (int j = 0; j < 8; ++j) {
+        const double t1[3] = {n1[1] * r1[2] - n1[2] * r1[1], n1[2] * r1[0] - n1[0] * r1[2],
+                              n1[0] * r1[1] - n1[1] * r1[0]};
+        const double t2[3] = {n2[1] * r2[2] - n2[2] * r2[1], n2[2] * r2[0] - n2[0] * r2[2],
+                              n2[0] * r2[1] - n2[1] * r2[0]};
+        double w[3];
+        for (int a = 0; a < 3; ++a) w[a] = (d[a] + A2 * r2[a]) - A1 * r1[a];
+        const double wt1 = w[0] * t1[0] + w[1] * t1[1] + w[2] * t1[2];
+        const double wt2 = w[0] * t2[0] + w[1] * t2[1] + w[2] * t2[2];
+        const double wr1 = w[0] * r1[0] + w[1] * r1[1] + w[2] * r1[2];
+        const double wr2 = w[0] * r2[0] + w[1] * r2[1] + w[2] * r2[2];
+        const double tt = t1[0] * t2[0] + t1[1] * t2[1] + t1[2] * t2[2];
+        const double g1 = -(A1 * wt1), g2 = A2 * wt2;
+        const double h11 = A1 * A1 + A1 * wr1, h22 = A2 * A2 - A2 * wr2, h12 = -(A1 * A2 * tt);
+        const double det = h11 * h22 - h12 * h12;
+        if (!(h11 > 0.0 && det > 0.0)) return -1;
+        const double s1 = -(h22 * g1 - h12 * g2) / det;
+        const double s2 = -(h11 * g2 - h12 * g1) / det;
+        for (int a = 0; a < 3; ++a) {
+            r1[a] = r1[a] + s1 * t1[a];
+            r2[a] = r2[a] + s2 * t2[a];
+        }
+        sd_unit(r1);
+        sd_unit(r2);
+        double p[3], q[3];
+        for (int a = 0; a < 3; ++a) {
+            p[a] = A1 * r1[a];
+            q[a] = d[a] + A2 * r2[a];
+        }
+        const int c = sd_certify(p, q, d, n1, A1, n2, A2, T);
+        if (c >= 0) return c;
+    }
+    return -1;
+}
+
+// Is the distance between core disk 1 (centre 0, n1, A1) and core disk 2
+// (centre d, n2, A2) at most T?  (The full search runs out of line.)
+__device__ __noinline__ bool sd_within_slow(const double d[3], const double n1[3], double A1,
+                                            const double n2[3], double A2, double T, double dd)
+{
+    double u[3];
+    if (dd > 0.0) {
+        const double r = __builtin_sqrt(dd);
+        u[0] = d[0] / r;
+        u[1] = d[1] / r;
+        u[2] = d[2] / r;
+        if (sd_lower(u, d, n1, A1, n2, A2) > T) return false;
+    }
+    const double h1 = n1[0] * d[0] + n1[1] * d[1] + n1[2] * d[2];
+    const double h2 = n2[0] * d[0] + n2[1] * d[1] + n2[2] * d[2];
+    for (int a = 0; a < 3; ++a) u[a] = (h1 >= 0.0) ? n1[a] : -n1[a];
+    if (sd_lower(u, d, n1, A1, n2, A2) > T) return false;
+    for (int a = 0; a < 3; ++a) u[a] = (h2 >= 0.0) ? n2[a] : -n2[a];
+    if (sd_lower(u, d, n1, A1, n2, A2) > T) return false;
+    double st1[2][3], st2[2][3];
+    int ns = 0;
+    const double c12 = n2[0] * n1[0] + n2[1] * n1[1] + n2[2] * n1[2];
+    double m[3] = {n2[0] - c12 * n1[0], n2[1] - c12 * n1[1], n2[2] - c12 * n1[2]};
+    double mm = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+    if (mm > 0.0) {
+        const double r = __builtin_sqrt(mm);
+        double p[3], x[3], y[3], q[3];
+        for (int a = 0; a < 3; ++a) {
+            const double e = m[a] / r;
+            p[a] = (h2 >= 0.0) ? A1 * e : -(A1 * e);
+            x[a] = p[a] - d[a];
+        }
+        const bool rim = sd_proj(x, n2, A2, y);
+        for (int a = 0; a < 3; ++a) q[a] = d[a] + y[a];
+        const int c = sd_certify(p, q, d, n1, A1, n2, A2, T);
+        if (c >= 0) return c == 1;
+        if (rim) {
+            for (int a = 0; a < 3; ++a) {
+                st1[ns][a] = p[a];
+                st2[ns][a] = y[a];
+            }
+            sd_unit(st1[ns]);
+            sd_unit(st2[ns]);
+            ++ns;
+        }
+    }
+    const double c21 = n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2];
+    m[0] = n1[0] - c21 * n2[0];
+    m[1] = n1[1] - c21 * n2[1];
+    m[2] = n1[2] - c21 * n2[2];
+    mm = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+    if (mm > 0.0) {
+        const double r = __builtin_sqrt(mm);
+        double y[3], q[3], p[3];
+        for (int a = 0; a < 3; ++a) {
+            const double e = m[a] / r;
+            y[a] = (h1 >= 0.0) ? -(A2 * e) : A2 * e;
+            q[a] = d[a] + y[a];
+        }
+        const bool rim = sd_proj(q, n1, A1, p);
+        const int c = sd_certify(p, q, d, n1, A1, n2, A2, T);
+        if (c >= 0) return c == 1;
+        if (rim) {
+            for (int a = 0; a < 3; ++a) {
+                st1[ns][a] = p[a];
+                st2[ns][a] = y[a];
+            }
+            sd_unit(st1[ns]);
+            sd_unit(st2[ns]);
+            ++ns;
+        }
+    }
+    double p[3], q[3], x[3], y[3];
+    sd_proj(d, n1, A1, p);
+    for (int k = 1; k <= 64; ++k) {
+        for (int a = 0; a < 3; ++a) x[a] = p[a] - d[a];
+        sd_proj(x, n2, A2, y);
+        for (int a = 0; a < 3; ++a) q[a] = d[a] + y[a];
+        sd_proj(q, n1, A1, p);
+        int c = sd_certify(p, q, d, n1, A1, n2, A2, T);
+        if (c >= 0) return c == 1;
+        if (k == 6) {
+            const double pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+            const double yy = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+            if (pp > 0.0 && yy > 0.0) {
+                double r1[3] = {p[0], p[1], p[2]}, r2[3] = {y[0], y[1], y[2]};
+                sd_unit(r1);
+                sd_unit(r2);
+                c = sd_newton(d, n1, A1, n2, A2, T, r1, r2);
+                if (c >= 0) return c == 1;
+            }
+            for (int j = 0; j < ns; ++j) {
+                c = sd_newton(d, n1, A1, n2, A2, T, st1[j], st2[j]);
+                if (c >= 0) return c == 1;
+            }
+        }
+    }
+    return true;
+}
+
+// Spherodisks with centres 0 and d (minimum image of c2 - c1, lower id as
+// disk 1), unit normals n1, n2, outer radii a1, a2, half-thicknesses
+// tau a: do they overlap when their shells are grown by gap?
+__device__ __forceinline__ bool spherodisks_overlap(double dx, double dy, double dz,
+                                                    const double n1[3], double a1,
+                                                    const double n2[3], double a2, double tau,
+                                                    double gap)
+{
+    const double h1 = tau * a1, h2 = tau * a2;
+    const double A1 = a1 - h1, A2 = a2 - h2;
+    const double T = (h1 + h2) + gap;
+    const double d[3] = {dx, dy, dz};
+    const double dd = dx * dx + dy * dy + dz * dz;
+    const double R = (A1 + A2) + T;
+    if (dd > R * R) return false;
+    if (disks_intersect(dx, dy, dz, n1, A1, n2, A2)) return true;
+    return sd_within_slow(d, n1, A1, n2, A2, T, dd);
+}
+
+// The contact test of two platelets: zero-thickness disks (SD false) or
+// spherodisks (SD true; tau = half-thickness / outer radius).
+template <bool SD>
+__device__ __forceinline__ bool platelets_touch(double dx, double dy, double dz,
+                                                const double n1[3], double a1,
+                                                const double n2[3], double a2, double tau)
+{
+    if (SD) return spherodisks_overlap(dx, dy, dz, n1, a1, n2, a2, tau, 0.0);
+    return disks_intersect(dx, dy, dz, n1, a1, n2, a2);
+}
+
 // Adaptive grid of Algorithm 1 for the largest radius rmax: cell edge
 // cs = 2.5 rmax + 2.5 c_m; per axis N_a = m - (m mod 2) cells if
 // m = min(floor(L_a / cs), ncap) >= 4, else one cell.  The same IEEE

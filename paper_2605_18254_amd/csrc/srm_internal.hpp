@@ -86,6 +86,7 @@ struct PassArgs {
     Draw draw;         // key, sweep, kind<<31 | k<<16 (trial l added per draw)
     int32_t n_l;
     double c_m, c_n;
+    double tau;            // platelets: half-thickness / outer radius (0: zero-thickness disks)
     int32_t *ovf;          // tiled kernel: per-colour overflow counts + tile lists
     int32_t ovf_max_tiles; // list capacity per colour
     int32_t *failed;       // [0] = count, then slots of particles that rejected every trial
@@ -107,10 +108,11 @@ hipError_t check_overlaps(int dim, int shape, bool poly, const PassArgs &a, bool
 // Pair enumeration and distance histogram of a binned configuration
 // (k_pairs.hip).  rowcnt/rowoff are indexed by particle id.
 hipError_t pairs_count(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
-                       int shape, double s, double gap, int32_t *rowcnt, hipStream_t stream);
+                       int shape, double tau, double s, double gap, int32_t *rowcnt,
+                       hipStream_t stream);
 hipError_t pairs_emit(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
-                      int shape, double s, double gap, const int32_t *rowoff, int32_t *partner,
-                      int32_t *ij, hipStream_t stream);
+                      int shape, double tau, double s, double gap, const int32_t *rowoff,
+                      int32_t *partner, int32_t *ij, hipStream_t stream);
 hipError_t rdf_counts(int dim, const PBuf &b, const int32_t *start, const Grid &g, int32_t n,
                       int32_t nbins, double inv, unsigned long long *counts, hipStream_t stream);
 // Percolation (k_perc.hip): bond image shifts, (label, offset) relaxation

@@ -17,8 +17,10 @@ by the workload seed):
 
 The target radius scale ``s_target`` is the scale at which the particle
 volumes fill the requested fraction of the box: ball volume omega_d R**d with
-omega_2 = pi, omega_3 = 4 pi / 3 (disks and spheres), and pi a**2 t with
-t = thick_ratio * 2a for thin circular platelets (cylinder model).
+omega_2 = pi, omega_3 = 4 pi / 3 (disks and spheres), pi a**2 t with
+t = thick_ratio * 2a for thin circular platelets (cylinder model), and the
+volume of a spherodisk of outer radius a and thickness t (a core disk of
+radius a - t/2 swept by a ball of radius t/2) for spherodisks.
 """
 from __future__ import annotations
 
@@ -30,6 +32,7 @@ import numpy as np
 
 BALL = 0
 PLATELET = 1
+SPHERODISK = 2
 
 
 @dataclasses.dataclass
@@ -112,6 +115,15 @@ def ball_volume_coeff(dim: int) -> float:
     return math.pi if dim == 2 else 4.0 * math.pi / 3.0
 
 
+def spherodisk_volume_coeff(thick_ratio: float) -> float:
+    """Volume of a spherodisk of outer radius 1 and thickness 2 thick_ratio:
+    core disk radius A = 1 - h swept by a ball of radius h = thick_ratio
+    (Steiner: 2 pi A^2 h + pi^2 A h^2 + 4/3 pi h^3)."""
+    h = thick_ratio
+    A = 1.0 - h
+    return 2.0 * math.pi * A * A * h + math.pi ** 2 * A * h * h + 4.0 / 3.0 * math.pi * h ** 3
+
+
 def target_scale(dim: int, shape: int, f_target: float, box, rho: Optional[np.ndarray],
                  n: int, thick_ratio: float = 0.01) -> float:
     """Scale s at which sum of particle volumes / box volume == f_target."""
@@ -119,6 +131,8 @@ def target_scale(dim: int, shape: int, f_target: float, box, rho: Optional[np.nd
     srd = float(n) if rho is None else float(np.sum(rho.astype(np.float64) ** dim))
     if shape == PLATELET:
         coeff = 2.0 * math.pi * thick_ratio  # pi a^2 (thick_ratio * 2 a)
+    elif shape == SPHERODISK:
+        coeff = spherodisk_volume_coeff(thick_ratio)
     else:
         coeff = ball_volume_coeff(dim)
     return (f_target * vbox / (coeff * srd)) ** (1.0 / dim)
@@ -128,7 +142,7 @@ def make(name: str = "disks2d", *, n: Optional[int] = None, dim: Optional[int] =
          seed: Optional[int] = None, f_target: Optional[float] = None,
          c_w: float = 0.01, c_m_rel: float = 0.1, n_k: int = 8, n_l: int = 8,
          polydisperse_sigma: Optional[float] = None, box=(1.0, 1.0, 1.0),
-         cap_deg: Optional[float] = None) -> Workload:
+         cap_deg: Optional[float] = None, aspect_ratio: Optional[float] = None) -> Workload:
     """Build a named workload, optionally overriding its size and seed.
 
     Named workloads:
@@ -138,6 +152,9 @@ def make(name: str = "disks2d", *, n: Optional[int] = None, dim: Optional[int] =
                  f_target 0.02, isotropic normals (cap_deg=15 for the
                  quasi-nematic start)
       softrdf    3D unit cube, N=2e5 spheres, seed 3, f_target 0.30
+      spherodisks 3D unit cube, N=2e4 spherodisks of aspect ratio D/t = 100
+                 (``aspect_ratio`` overrides it), seed 4, f_target 0.02,
+                 isotropic normals (cap_deg as for platelets)
     c_m = c_m_rel * s_target (migration step of a tenth of the final radius).
     """
     defaults = {
@@ -145,6 +162,7 @@ def make(name: str = "disks2d", *, n: Optional[int] = None, dim: Optional[int] =
         "spheres3d": dict(dim=3, n=10_000_000, seed=1, f_target=0.35, shape=BALL),
         "platelets": dict(dim=3, n=200_000, seed=2, f_target=0.02, shape=PLATELET),
         "softrdf": dict(dim=3, n=200_000, seed=3, f_target=0.30, shape=BALL),
+        "spherodisks": dict(dim=3, n=20_000, seed=4, f_target=0.02, shape=SPHERODISK),
     }
     if name not in defaults:
         raise KeyError(f"unknown workload {name!r}")
@@ -162,16 +180,17 @@ def make(name: str = "disks2d", *, n: Optional[int] = None, dim: Optional[int] =
     pos = uniform_points(n_, dim_, seed_, box3)
     rho = None if polydisperse_sigma is None else lognormal_rho(n_, seed_, polydisperse_sigma)
     normals = None
-    thick = 0.01
-    if shape == PLATELET:
+    thick = 0.01 if aspect_ratio is None else 1.0 / float(aspect_ratio)
+    disk = shape in (PLATELET, SPHERODISK)
+    if disk:
         normals = (cap_normals(n_, seed_, cap_deg) if cap_deg is not None
                    else isotropic_normals(n_, seed_))
     s_t = target_scale(dim_, shape, d["f_target"], box3, rho, n_, thick)
     c_m = c_m_rel * s_t
-    c_n = c_m / s_t if shape == PLATELET else 0.0
+    c_n = c_m / s_t if disk else 0.0
     return Workload(name=name, dim=dim_, shape=shape, n=n_, box=box3,
                     f_target=d["f_target"], s_target=s_t, c_w=c_w, c_m=c_m, c_n=c_n,
-                    thick_ratio=thick if shape == PLATELET else 0.0, n_k=n_k, n_l=n_l,
+                    thick_ratio=thick if disk else 0.0, n_k=n_k, n_l=n_l,
                     seed=seed_, pos=pos, rho=rho, normals=normals)
 
 
