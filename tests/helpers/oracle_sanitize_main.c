@@ -21,13 +21,15 @@ static int run_case(int dim, int shape, int64_t n, int poly, double box_z)
     p->dim = dim; p->shape = shape; p->n = n;
     p->box[0] = 1.0; p->box[1] = 0.9; p->box[2] = box_z;
     double vol = (dim == 3) ? 0.9 * box_z : 0.9;
-    double f = shape == O_PLATELET ? 0.01 : 0.3;
-    double coeff = shape == O_PLATELET ? 2.0 * M_PI * 0.01 : (dim == 2 ? M_PI : 4.0 * M_PI / 3.0);
+    int disk = shape == O_PLATELET || shape == O_SPHERODISK;
+    double tr = shape == O_SPHERODISK ? 0.1 : 0.01;
+    double f = disk ? 0.01 : 0.3;
+    double coeff = disk ? 2.0 * M_PI * tr : (dim == 2 ? M_PI : 4.0 * M_PI / 3.0);
     p->s_target = pow(f * vol / (coeff * (double)n), 1.0 / dim);
-    p->c_w = 0.05; p->c_m = 0.1 * p->s_target; p->c_n = 0.1; p->thick_ratio = 0.01;
+    p->c_w = 0.05; p->c_m = 0.1 * p->s_target; p->c_n = 0.1; p->thick_ratio = tr;
     p->n_k = 4; p->n_l = 6; p->seed = 77;
     st.pos = (double *)calloc(3 * (size_t)n, sizeof(double));
-    st.nrm = shape == O_PLATELET ? (double *)calloc(3 * (size_t)n, sizeof(double)) : NULL;
+    st.nrm = disk ? (double *)calloc(3 * (size_t)n, sizeof(double)) : NULL;
     double *rho = poly ? (double *)malloc(sizeof(double) * (size_t)n) : NULL;
     for (int64_t i = 0; i < n; ++i) {
         for (int a = 0; a < dim; ++a) st.pos[3 * i + a] = urand() * p->box[a];
@@ -90,6 +92,8 @@ int main(void)
     bad |= run_case(3, O_BALL, 600, 0, 1.2);
     bad |= run_case(3, O_BALL, 500, 1, 0.8);
     bad |= run_case(3, O_PLATELET, 300, 0, 1.0);
+    bad |= run_case(3, O_SPHERODISK, 300, 0, 1.0);
+    bad |= run_case(3, O_SPHERODISK, 200, 1, 0.9);
     bad |= run_case(2, O_BALL, 1, 0, 1.0);
     /* RSA, balls and platelets, and a budget that runs out */
     double box[3] = {1.0, 1.0, 1.0};

@@ -1,6 +1,6 @@
 """The oracle built with gcc's address and undefined-behaviour sanitizers
-runs every entry point (sweeps to the target for disks, spheres and
-platelets, mono- and polydisperse, masked passes, global checks, pairs,
+runs every entry point (sweeps to the target for disks, spheres,
+platelets and spherodisks, mono- and polydisperse, masked passes, global checks, pairs,
 percolation, distance histogram, nearest neighbours, soft g(r) and its
 gradient, RSA) without a report (CPU only)."""
 import os
