@@ -649,32 +649,57 @@ def grad_extra(steps, steer_steps):
     torch.cuda.synchronize()
     ms_fwd = fwd0.elapsed_time(fwd1) / steps
     ms_step = s0.elapsed_time(s1) / steps
-    ctx = srm.SRM(dim=3, n=w.n, s_target=r, c_w=0.0, c_m=w.c_m, n_k=8, n_l=8, seed=w.seed,
-                  pos=pos, s0=r, sweep0=run["sweeps"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    hist = softrdf.steer(ctx, ws, target, r, steps=steer_steps, max_step=0.5 * w.c_m)
-    torch.cuda.synchronize()
-    dt_steer = time.perf_counter() - t0
-    _, _, s_fin, _ = ctx.state()
-    overlaps = len(ctx.pairs(0.0))
-    ctx.close()
+    # steering toward two readings of the clustered target: parents at
+    # 1e-3 N per unit volume (literal; g(0) ~ 12.6, far beyond what a hard
+    # sphere fluid at f = 0.30 can reach) and N / 50 parents (every point in
+    # a cluster of 50; g(0) ~ 1.58)
+    steer_out = {}
+    for name, parents in (("parents_1e-3N", 1e-3 * w.n), ("parents_N_over_50", w.n / 50.0)):
+        tgt = softrdf.thomas_g(centres, parents, 3.0 * r)
+        tgt = torch.where(centres < 2 * r, torch.zeros_like(tgt), tgt)
+        ctx = srm.SRM(dim=3, n=w.n, s_target=r, c_w=0.0, c_m=0.02 * r, n_k=8, n_l=8,
+                      seed=w.seed, pos=pos, s0=r, sweep0=run["sweeps"])
+        with torch.no_grad():
+            g_first, _ = ws.forward(pos, radii)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = softrdf.steer(ctx, ws, tgt, r, steps=steer_steps, max_step=0.5 * w.c_m)
+        torch.cuda.synchronize()
+        dt_steer = time.perf_counter() - t0
+        fin = torch.empty_like(pos)
+        ctx.state_device(fin)
+        _, _, s_fin, _ = ctx.state()
+        g_last, _ = ws.forward(fin, radii)
+        overlaps = len(ctx.pairs(0.0))
+        ctx.close()
+        losses = [h[0] for h in hist]
+        pick = list(range(0, nb, 8))
+        steer_out[name] = {
+            "steps": steer_steps, "s": dt_steer, "ms_per_step": dt_steer / steer_steps * 1e3,
+            "kept": sum(1 for h in hist[1:] if h[1]),
+            "loss_first": losses[0], "loss_last": losses[-1],
+            "loss_decrease": 1.0 - losses[-1] / losses[0],
+            "monotone": all(b <= a for a, b in zip(losses, losses[1:])),
+            "bins_r_over_radius": [round(float(centres[b] / r), 3) for b in pick],
+            "g_target": [round(float(tgt[b]), 4) for b in pick],
+            "g_first": [round(float(g_first[b]), 4) for b in pick],
+            "g_last": [round(float(g_last[b]), 4) for b in pick],
+            "s_over_s_target": s_fin / r, "overlapping_pairs": overlaps}
+        _say(f"steering {name}: {steer_out[name]}")
     ws.close()
     return {
         "workload": "spheres3d N=2e5 f=0.30 seed 3; soft g(r) 64 bins on [0, 5r], h = bin "
-                    "width, C2 taper to 5r+4h; target Thomas process (parent density "
-                    "1e-3 N, sigma 3r); loss |g - target|^2 + E",
+                    "width, C2 taper to 5r+4h; target Thomas process (sigma 3r, two parent "
+                    "densities), 0 below 2r; loss |g - target|^2 + E; steering: monotone "
+                    "line search, largest move <= c_m/2, SRM sweep with c_w 0 and c_m 0.02 r "
+                    "after each step",
         "grow_to_fraction": {"s": dt_grow, "sweeps": run["sweeps"],
                              "updates_per_s": run["updates"] / dt_grow,
                              "fraction": run["fraction"]},
         "pairs_within_cutoff": pairs,
         "ms_forward": ms_fwd, "ms_forward_backward": ms_step,
         "pair_evals_per_s": 3 * pairs / (ms_step / 1e3),
-        "steer": {"steps": steer_steps, "s": dt_steer,
-                  "ms_per_step": dt_steer / steer_steps * 1e3,
-                  "accepted": sum(1 for _, a in hist if a),
-                  "loss_first": hist[0][0], "loss_last": hist[-1][0],
-                  "s_over_s_target": s_fin / r, "overlapping_pairs": overlaps},
+        "steer": steer_out,
     }
 
 
@@ -863,7 +888,7 @@ def main():
                 "platelet_protocol": platelet_protocol_extra,
                 "spherodisk_protocol": spherodisk_protocol_extra,
                 "batched": lambda: batched_extra(args.batch_sweeps),
-                "gradient": lambda: grad_extra(20, 10)}
+                "gradient": lambda: grad_extra(20, 100)}
         unknown = [x for x in names if x not in runs and x != "at_target"]
         if unknown:
             raise SystemExit(f"unknown extras: {unknown}")

@@ -158,32 +158,56 @@ def set_positions(srm: SRM, pos: torch.Tensor):
 
 
 def steer(srm: SRM, ws: SoftRDF, target: torch.Tensor, radius: float, steps: int,
-          max_step: float, lam: float = 1.0):
-    """Gradient steps on L = |g - target|^2 + lam * E with respect to the
-    positions, scaled so that no particle moves more than max_step; after
-    each step an SRM sweep (the context's c_w should be 0) must commit an
-    overlap-free state, else the step is undone.  Returns the per-step
-    (loss, accepted) history."""
+          max_step: float, lam: float = 1.0, tries: int = 6, grow: float = 1.25):
+    """Monotone descent of L = |g - target|^2 + lam * E over the positions.
+
+    A step moves every particle along -dL/dx, scaled so that the largest move
+    is eta (at most max_step).  An SRM sweep (the context's c_w should be 0
+    and its c_m small) then has to commit an overlap-free state -- SRM's exact
+    test judges admissibility -- and the loss of that committed state has to
+    be below the current loss; otherwise the step is undone and retried with
+    eta halved, up to `tries` times.  A kept step lets eta grow by `grow`.
+    Returns the history [(loss, kept, eta)] after each step, the first entry
+    being the starting loss."""
     dim, n = srm.dim, srm.n
     box = torch.tensor(list(srm.params.box)[:dim], dtype=torch.float64, device="cuda")
     pos = torch.empty((dim, n), dtype=torch.float64, device="cuda")
+    cand = torch.empty_like(pos)
     radii = torch.full((n,), float(radius), dtype=torch.float64, device="cuda")
-    hist = []
-    for _ in range(steps):
-        srm.state_device(pos)
-        p = pos.clone().requires_grad_(True)
+
+    def loss_and_grad(x):
+        p = x.clone().requires_grad_(True)
         g, e = soft_rdf(p, radii, ws)
         loss = ((g - target) ** 2).sum() + lam * e
         loss.backward()
-        with torch.no_grad():
-            gmax = float(p.grad.abs().max())
-            lr = max_step / gmax if gmax > 0 else 0.0
-            new = p - lr * p.grad
-            new = torch.remainder(new, box[:, None])
-            new = torch.where(new >= box[:, None], new - box[:, None], new)
-        set_positions(srm, new)
-        info = srm.sweep()
-        if not info["committed"]:
+        return float(loss.detach()), p.grad.detach()
+
+    srm.state_device(pos)
+    loss0, grad = loss_and_grad(pos)
+    eta = float(max_step)
+    hist = [(loss0, True, 0.0)]
+    for _ in range(steps):
+        kept = False
+        for _t in range(tries):
+            gmax = float(grad.abs().max())
+            if gmax == 0.0:
+                break
+            with torch.no_grad():
+                new = pos - (eta / gmax) * grad
+                new = torch.remainder(new, box[:, None])
+                new = torch.where(new >= box[:, None], new - box[:, None], new)
+            set_positions(srm, new)
+            info = srm.sweep()
+            if info["committed"]:
+                srm.state_device(cand)
+                loss1, grad1 = loss_and_grad(cand)
+                if loss1 < loss0:
+                    pos.copy_(cand)
+                    loss0, grad = loss1, grad1
+                    eta = min(eta * grow, float(max_step))
+                    kept = True
+                    break
             set_positions(srm, pos)
-        hist.append((float(loss.detach()), bool(info["committed"])))
+            eta *= 0.5
+        hist.append((loss0, kept, eta))
     return hist
