@@ -288,13 +288,36 @@ def batched_extra(max_sweeps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     upd_s = 0
+    solo = []  # (converged, seconds, updates) per RVE
     for r, g in enumerate(ctxs):
-        upd_s += g.run(max_sweeps)[1]["updates"]
+        t1 = time.perf_counter()
+        st_r, info_r = g.run(max_sweeps)
+        torch.cuda.synchronize()
+        solo.append((st_r == 0, time.perf_counter() - t1, info_r["updates"]))
+        upd_s += info_r["updates"]
         if r % 32 == 31:
             _say(f"sequential: {r + 1} RVEs, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     dt_s = time.perf_counter() - t0
     _say(f"sequential: {dt_s:.2f} s")
+    # the same comparison on the RVEs that reach their target, at the same
+    # final fraction: a batch of those alone against their solo runs
+    conv = [r for r in range(len(ws)) if solo[r][0]]
+    bc = Batch([ws[r] for r in conv])
+    bc.configure(*shape)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_c, info_c = bc.run(max_sweeps)
+    torch.cuda.synchronize()
+    dt_bc = time.perf_counter() - t0
+    conv_identical = True
+    for k, r in enumerate(conv):
+        pos_b, s_b, t_b, _ = bc.get(k)
+        pos_s, _, s_s, t_s = ctxs[r].state()
+        conv_identical = conv_identical and np.array_equal(pos_b, pos_s) and s_b == s_s and t_b == t_s
+    bc.close()
+    dt_sc = sum(solo[r][1] for r in conv)
+    upd_c = sum(solo[r][2] for r in conv)
     identical, overlaps, fr_b = True, 0, []
     for r, g in enumerate(ctxs):
         pos_b, s_b, t_b, _ = b.get(r)
@@ -317,6 +340,12 @@ def batched_extra(max_sweeps):
                     "graph_replays": info["replays"]},
         "sequential": {"s": dt_s, "updates_per_s": upd_s / dt_s},
         "speedup": dt_s / dt_b,
+        "converged_subset": {
+            "rves": len(conv), "all_at_target": st_c == 0 and info_c["converged"] == len(conv),
+            "bitidentical_to_solo": conv_identical,
+            "batched": {"s": dt_bc, "updates_per_s": upd_c / dt_bc},
+            "sequential": {"s": dt_sc, "updates_per_s": upd_c / dt_sc},
+            "speedup": dt_sc / dt_bc},
     }
 
 
