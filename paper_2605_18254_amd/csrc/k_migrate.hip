@@ -55,7 +55,10 @@ __global__ void __launch_bounds__(64) k_migrate_wave(PassArgs a, ColourLattice L
 //     during this colour phase, and every particle a trial within c_m of the
 //     old position can touch is among them (the exact test decides).
 //  B. the sequential part, one quad per cell, particles in ascending id
-//     order: lane j of the quad draws trial l = base + j and tests it exactly
+//     order.  Each particle's first trial free of its near list is found
+//     beforehand (lane per particle for trial 1, the whole quad four trials
+//     at a time for the rest) and settled against the cell mates; failing
+//     that, lane j of the quad draws trial l = base + j and tests it exactly
 //     against the near list and the other particles of its own cell at their
 //     current positions; the lowest collision-free trial of the batch is
 //     accepted -- the first free trial of the sequential rule, since all
@@ -293,6 +296,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, const TileLattice &
     __shared__ uint16_t obase[65];
     __shared__ uint16_t nearl[C::kOwn][C::kNear];
     __shared__ int32_t ncnt[C::kOwn];  // near-list lengths (may exceed kNear: overflow)
+    __shared__ uint8_t own_k[C::kOwn];  // own particle -> its own-cell slot (phase A)
     __shared__ int32_t wtot[4];
 
     // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous
@@ -418,6 +422,8 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, const TileLattice &
         const int32_t incl = wave_inclusive_scan(m_);
         obase[tid] = (uint16_t)(incl - m_);
         if (tid == 63) obase[64] = (uint16_t)(incl > 65535 ? 65535 : incl);
+        if (incl <= C::kOwn)
+            for (int32_t j = incl - m_; j < incl; ++j) own_k[j] = (uint8_t)tid;
     }
     for (int32_t o = tid; o < C::kOwn; o += 256) ncnt[o] = 0;
     __syncthreads();
@@ -432,12 +438,7 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, const TileLattice &
         constexpr int kRowsA = Rows<DIM>::kRows;
         for (int32_t w = tid; w < nown * kRowsA; w += 256) {
             const int32_t o = w / kRowsA, row = w - o * kRowsA;
-            int32_t klo = 0, khi = 63;
-            while (klo < khi) {
-                const int32_t mid = (klo + khi + 1) >> 1;
-                if (obase[mid] <= o) klo = mid;
-                else khi = mid - 1;
-            }
+            const int32_t klo = own_k[o];
             int32_t lx_, ly_, lz_;
             bool act_;
             own_cell(klo, lx_, ly_, lz_, act_);
@@ -479,47 +480,96 @@ __device__ __forceinline__ void tile_pass(const PassArgs &a, const TileLattice &
 
     // Groups of up to four particles of the cell.  The near list holds only
     // other cells' particles, which no lane moves during this colour phase,
-    // so lane `sub` first finds, for particle g0 + sub, its first trial that
-    // meets no near-list candidate (trials before it are rejected whatever
-    // the cell mates do).  Then the group is settled in id order: that trial
+    // so each particle's first trial that meets no near-list candidate can be
+    // found before any cell mate settles (trials before it are rejected
+    // whatever the cell mates do): lane `sub` draws trial 1 of particle
+    // g0 + sub, and for each particle whose trial 1 meets the list the quad
+    // draws its later trials four at a time, so no lane waits on another
+    // lane's long run of trials.  Then the group is settled in id order: that trial
     // is accepted if it also misses the cell mates at their current
     // positions; otherwise (or without a near list) the quad tests the
     // remaining trials four at a time against the whole neighbourhood.
     // Either way each particle takes its first free trial, in id order.
     for (int32_t g0 = ob; g0 < oe; g0 += 4) {
         const int32_t ps = g0 + sub;
-        bool spec = false;
+        bool spec = false, pend = false;
         int32_t l1 = 0;  // first near-free trial of particle ps (0: none)
         double sx1 = 0.0, sy1 = 0.0, sz1 = 0.0;
         if (ps < oe) {
             const int32_t o = o0 + (ps - ob);
-            if (use_near && ncnt[o] <= C::kNear) {
-                spec = true;
-                const int32_t nn = ncnt[o];
+            spec = use_near && ncnt[o] <= C::kNear;
+            if (spec && a.n_l >= 1) {
                 const double px = sx[ps], py = sy[ps], pz = (DIM == 3) ? sz[ps] : 0.0;
                 const double Ri = POLY ? a.s * srho[ps] : a.s;
                 const uint32_t id = (uint32_t)a.buf.id[gb + (ps - ob)];
                 Draw d = a.draw;
-                for (int32_t l = 1; l <= a.n_l; ++l) {
+                double v[3];
+                d.word = a.draw.word | (1u << 8);
+                unit_vector<DIM>(d, id, 0, a.c_m, v);
+                const double yx = wrap_coord(px + v[0], a.g.box[0]);
+                const double yy = wrap_coord(py + v[1], a.g.box[1]);
+                const double yz = (DIM == 3) ? wrap_coord(pz + v[2], a.g.box[2]) : 0.0;
+                const bool hit =
+                    general ? near_hits<DIM, POLY, true>(a, sx, sy, sz, srho, nearl[o], ncnt[o],
+                                                         yx, yy, yz, Ri)
+                            : near_hits<DIM, POLY, false>(a, sx, sy, sz, srho, nearl[o], ncnt[o],
+                                                          yx, yy, yz, Ri);
+                if (!hit) {
+                    l1 = 1;
+                    sx1 = yx;
+                    sy1 = yy;
+                    sz1 = yz;
+                } else {
+                    pend = a.n_l > 1;
+                }
+            }
+        }
+        // Particles whose first trial meets the near list: the quad tests
+        // their later trials four at a time, one particle after another.
+        for (uint32_t pm = quad_bits(__ballot(pend)); pm != 0; pm &= pm - 1) {
+            const int32_t j = __ffs(pm) - 1;
+            const int32_t pj = g0 + j;
+            const int32_t oj = o0 + (pj - ob);
+            const double px = sx[pj], py = sy[pj], pz = (DIM == 3) ? sz[pj] : 0.0;
+            const double Rj = POLY ? a.s * srho[pj] : a.s;
+            const uint32_t idj = (uint32_t)a.buf.id[gb + (pj - ob)];
+            const int32_t nnj = ncnt[oj];
+            int32_t found = 0;
+            double fx = 0.0, fy = 0.0, fz = 0.0;
+            Draw d = a.draw;
+            for (int32_t base = 2; base <= a.n_l; base += 4) {
+                const int32_t l = base + sub;
+                bool free_ = false;
+                double yx = 0.0, yy = 0.0, yz = 0.0;
+                if (l <= a.n_l) {
                     double v[3];
                     d.word = a.draw.word | ((uint32_t)l << 8);
-                    unit_vector<DIM>(d, id, 0, a.c_m, v);
-                    const double yx = wrap_coord(px + v[0], a.g.box[0]);
-                    const double yy = wrap_coord(py + v[1], a.g.box[1]);
-                    const double yz = (DIM == 3) ? wrap_coord(pz + v[2], a.g.box[2]) : 0.0;
-                    const bool hit =
-                        general ? near_hits<DIM, POLY, true>(a, sx, sy, sz, srho, nearl[o], nn, yx,
-                                                             yy, yz, Ri)
-                                : near_hits<DIM, POLY, false>(a, sx, sy, sz, srho, nearl[o], nn,
-                                                              yx, yy, yz, Ri);
-                    if (!hit) {
-                        l1 = l;
-                        sx1 = yx;
-                        sy1 = yy;
-                        sz1 = yz;
-                        break;
-                    }
+                    unit_vector<DIM>(d, idj, 0, a.c_m, v);
+                    yx = wrap_coord(px + v[0], a.g.box[0]);
+                    yy = wrap_coord(py + v[1], a.g.box[1]);
+                    yz = (DIM == 3) ? wrap_coord(pz + v[2], a.g.box[2]) : 0.0;
+                    free_ = !(general ? near_hits<DIM, POLY, true>(a, sx, sy, sz, srho, nearl[oj],
+                                                                   nnj, yx, yy, yz, Rj)
+                                      : near_hits<DIM, POLY, false>(a, sx, sy, sz, srho,
+                                                                    nearl[oj], nnj, yx, yy, yz,
+                                                                    Rj));
                 }
+                const uint32_t fb = quad_bits(__ballot(free_));
+                if (fb) {
+                    const int win = __ffs(fb) - 1;
+                    const int32_t src = (tid & 63 & ~3) | win;
+                    found = base + win;
+                    fx = __shfl(yx, src, 64);
+                    fy = __shfl(yy, src, 64);
+                    fz = __shfl(yz, src, 64);
+                    break;
+                }
+            }
+            if (sub == j) {
+                l1 = found;
+                sx1 = fx;
+                sy1 = fy;
+                sz1 = fz;
             }
         }
         const int32_t gend = (oe - g0 < 4) ? oe : g0 + 4;
