@@ -197,7 +197,10 @@ struct WaveLds {
     int32_t near[kWaveOwn * kWaveNear];  // slot q >= 0, or -(k + 1) for own particle k
     int32_t id[kWaveOwn];
     int32_t nfail;
-    int32_t fail[kWaveOwn];  // own indices that rejected every trial
+    union {
+        int32_t fail[kWaveOwn];  // phase B: own indices that rejected every trial
+        int32_t kept[128];       // phase A: stencil candidates near the cell, queued
+    };
 };
 
 template <int DIM>
@@ -286,6 +289,7 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
     const double *__restrict__ Z = a.buf.x[2];
     int32_t lo[Rows<DIM>::kRanges], hi[Rows<DIM>::kRanges];
     stencil_slices<DIM>(a.g, a.start, cx, cy, cz, lo, hi);
+    float rmax32 = 0.0f;  // largest own radius, for the cell-box filter below
     for (int32_t k = lane; k < cnt; k += 64) {
         WaveOwn o;
         o.x = X[beg + k];
@@ -294,9 +298,12 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
         o.r = POLY ? a.s * a.buf.rho[beg + k] : a.s;
         L.own[k] = o;
         L.own32[k] = make_float4((float)o.x, (float)o.y, (float)o.z, (float)o.r);
+        rmax32 = fmaxf(rmax32, (float)o.r);
         L.nn[k] = 0;
         L.id[k] = a.buf.id[beg + k];
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) rmax32 = fmaxf(rmax32, __shfl_xor(rmax32, o, 64));
     if (lane == 0) L.nfail = 0;
     __syncthreads();
     // A. near lists.  A list only has to contain every candidate that can
@@ -327,21 +334,81 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
         return qq <= rr * rr;
     };
     const float cm2 = (float)(2.0 * a.c_m), cm3 = (float)(3.0 * a.c_m);
+    // Every own particle sits in the cell's box (binned this pass, not yet
+    // moved), so a candidate farther from the box than R_q + max R_own +
+    // 2 c_m meets none of them.  The box test keeps a superset of what the
+    // pair filter keeps (three times its rounding margin), and with a cell
+    // edge set by the largest radius it drops most of the stencil.  Kept
+    // candidates queue in LDS and are tested against the own particles 64 at
+    // a time, so the lanes of a pass all carry one.
+    const double wxd = a.g.box[0] / (double)a.g.na[0], wyd = a.g.box[1] / (double)a.g.na[1];
+    const double wzd = (DIM == 3) ? a.g.box[2] / (double)a.g.na[2] : 0.0;
+    const float ccx = (float)((cx + 0.5) * wxd), ccy = (float)((cy + 0.5) * wyd);
+    const float ccz = (float)((cz + 0.5) * wzd);
+    const float hwx = (float)(0.5 * wxd), hwy = (float)(0.5 * wyd), hwz = (float)(0.5 * wzd);
+    auto box_gap = [](float d, float h, float b, float hw) {
+        if (d > h) d -= b;
+        if (d < -h) d += b;
+        const float g = fabsf(d) - hw;
+        return g > 0.0f ? g : 0.0f;
+    };
+    auto pair_pass = [&](int32_t q) {
+        const float qx = (float)X[q], qy = (float)Y[q], qz = (DIM == 3) ? (float)Z[q] : 0.0f;
+        const float Rq = (float)(POLY ? a.s * a.buf.rho[q] : a.s);
+        for (int32_t k = 0; k < cnt; ++k) {
+            const float4 o = L.own32[k];
+            if (near32(o, qx, qy, qz, (o.w + Rq) + cm2)) {
+                const int32_t slot = atomicAdd(&L.nn[k], 1);
+                if (slot < kWaveNear) L.near[k * kWaveNear + slot] = q;
+            }
+        }
+    };
+    int32_t nk = 0;  // queued candidates (the same in every lane)
 #pragma unroll
     for (int r = 0; r < Rows<DIM>::kRanges; ++r) {
-        for (int32_t q = lo[r] + lane; q < hi[r]; q += 64) {
-            if (q >= beg && q < end) continue;
-            const float qx = (float)X[q], qy = (float)Y[q], qz = (DIM == 3) ? (float)Z[q] : 0.0f;
-            const float Rq = (float)(POLY ? a.s * a.buf.rho[q] : a.s);
-            for (int32_t k = 0; k < cnt; ++k) {
-                const float4 o = L.own32[k];
-                if (near32(o, qx, qy, qz, (o.w + Rq) + cm2)) {
-                    const int32_t slot = atomicAdd(&L.nn[k], 1);
-                    if (slot < kWaveNear) L.near[k * kWaveNear + slot] = q;
+        for (int32_t q0 = lo[r]; q0 < hi[r]; q0 += 64) {
+            const int32_t q = q0 + lane;
+            bool keep = false;
+            if (q < hi[r] && !(q >= beg && q < end)) {
+                const float qx = (float)X[q], qy = (float)Y[q];
+                const float qz = (DIM == 3) ? (float)Z[q] : 0.0f;
+                const float Rq = (float)(POLY ? a.s * a.buf.rho[q] : a.s);
+                const float gx = box_gap(qx - ccx, hx32, bx32, hwx);
+                const float gy = box_gap(qy - ccy, hy32, by32, hwy);
+                float g2 = gx * gx + gy * gy;
+                if (DIM == 3) {
+                    const float gz = box_gap(qz - ccz, hz32, bz32, hwz);
+                    g2 = g2 + gz * gz;
                 }
+                const float rr = ((Rq + rmax32) + cm2) * 1.00001f + 3.0f * tol32;
+                keep = g2 <= rr * rr;
+            }
+            const unsigned long long km = __ballot(keep);
+            if (keep) {
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+                L.kept[nk + (int32_t)below] = q;
+            }
+            nk += __popcll(km);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (nk >= 64) {
+                pair_pass(L.kept[lane]);
+                const int32_t rem = nk - 64;
+                const int32_t mv = (lane < rem) ? L.kept[64 + lane] : 0;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (lane < rem) L.kept[lane] = mv;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                nk = rem;
             }
         }
     }
+    if (lane < nk) pair_pass(L.kept[lane]);
     for (int32_t j = lane; j < cnt; j += 64) {
         const float4 b = L.own32[j];
         for (int32_t k = 0; k < cnt; ++k) {
@@ -375,13 +442,27 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
         for (int32_t l = 1; l <= a.n_l; ++l) {
             double yx, yy, yz;
             wave_trial<DIM>(a, id, l, me.x, me.y, me.z, yx, yy, yz);
+            // near entries four at a time: their loads are issued together
             bool hit = false;
-            for (int32_t e = 0; e < m && !hit; ++e) {
-                const int32_t ref = L.near[k * kWaveNear + e];
-                if (ref >= 0)
-                    hit = wave_hit<DIM, POLY>(a, yx, yy, yz, me.r, X[ref], Y[ref],
-                                              (DIM == 3) ? Z[ref] : 0.0,
-                                              POLY ? a.s * a.buf.rho[ref] : a.s);
+            for (int32_t e = 0; e < m && !hit; e += 4) {
+                int32_t rf[4];
+                double qx[4], qy[4], qz[4], qr[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    rf[i] = (e + i < m) ? L.near[k * kWaveNear + e + i] : -1;
+                    qx[i] = qy[i] = qz[i] = qr[i] = 0.0;
+                    if (rf[i] >= 0) {
+                        qx[i] = X[rf[i]];
+                        qy[i] = Y[rf[i]];
+                        if (DIM == 3) qz[i] = Z[rf[i]];
+                        qr[i] = POLY ? a.s * a.buf.rho[rf[i]] : a.s;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (rf[i] >= 0)
+                        hit = hit || wave_hit<DIM, POLY>(a, yx, yy, yz, me.r, qx[i], qy[i], qz[i],
+                                                         qr[i]);
             }
             if (!hit) {
                 spec[h] = l;

@@ -204,6 +204,21 @@ def test_tile_variants_bitexact(srm, oracle_lib, sigma, seed, f, bits):
     g.close()
 
 
+@pytest.mark.parametrize("n_l", [3, 5, 13])
+def test_tile_trial_counts_bitexact(srm, oracle_lib, n_l):
+    """Dense packings make many first trials meet the near list; the LDS tile
+    then draws a particle's later trials four at a time across its quad (one
+    batch for N_l = 5, three for 13, a partial one for 3).  Thirty sweeps
+    toward f = 0.45 (f 0.17 to 0.30 at the end, as N_l allows) equal the
+    oracle, accept codes included."""
+    w = _mk(3, 20000, 76 + n_l, 0.45, c_w=0.03, n_l=n_l)
+    o, g, sweeps = _sweep_parity(srm, oracle_lib, w, 30, every=3, profile=True)
+    assert sweeps == 30
+    assert g.profile()["main_kernels"] & 1
+    _say(f"n_l={n_l}: {sweeps} sweeps")
+    g.close()
+
+
 @pytest.mark.parametrize("dim,n,box,f", [(3, 20000, (1.0, 0.6, 1.5), 0.35),
                                          (2, 4000, (1.0, 2.5), 0.5)])
 def test_stretched_box_bitexact(srm, oracle_lib, dim, n, box, f):
