@@ -159,17 +159,34 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *lds_
     return wave_off + inc - v;
 }
 
+// A thread's kScanItems consecutive counts, as two 16-byte loads when the
+// array is 16-byte aligned and the run lies wholly inside it.
+__device__ __forceinline__ void load_items(const int32_t *__restrict__ in, int64_t base, int32_t m,
+                                           bool vec, int32_t v[kScanItems])
+{
+    static_assert(kScanItems == 8, "two int4 per thread");
+    if (vec && base + kScanItems <= m) {
+        const int4 a = *reinterpret_cast<const int4 *>(in + base);
+        const int4 b = *reinterpret_cast<const int4 *>(in + base + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < m) ? in[base + k] : 0;
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_scan_partials(const int32_t *__restrict__ in,
                                                           int32_t m, int32_t *__restrict__ partials)
 {
     __shared__ int32_t lds[kBlock / 64];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const bool vec = ((uintptr_t)in & 15) == 0;
+    int32_t v[kScanItems];
+    load_items(in, base, m, vec, v);
     int32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t i = base + k;
-        if (i < m) s += in[i];
-    }
+    for (int k = 0; k < kScanItems; ++k) s += v[k];
     s = wave_sum(s);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) lds[wid] = s;
@@ -205,21 +222,27 @@ __global__ void __launch_bounds__(kBlock) k_scan_final(const int32_t *__restrict
 {
     __shared__ int32_t lds[kBlock / 64];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const bool vec = ((uintptr_t)in & 15) == 0 && ((uintptr_t)out & 15) == 0;
     int32_t v[kScanItems];
+    load_items(in, base, m, vec, v);
     int32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t i = base + k;
-        v[k] = (i < m) ? in[i] : 0;
-        s += v[k];
-    }
+    for (int k = 0; k < kScanItems; ++k) s += v[k];
     int32_t tot;
     int32_t run = partials[blockIdx.x] + block_exclusive_scan(s, lds, &tot);
+    int32_t o[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const int64_t i = base + k;
-        if (i < m) out[i] = run;
+        o[k] = run;
         run += v[k];
+    }
+    if (vec && base + kScanItems <= m) {
+        *reinterpret_cast<int4 *>(out + base) = make_int4(o[0], o[1], o[2], o[3]);
+        *reinterpret_cast<int4 *>(out + base + 4) = make_int4(o[4], o[5], o[6], o[7]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < m) out[base + k] = o[k];
     }
 }
 

@@ -742,6 +742,58 @@ __global__ void __launch_bounds__(kBlock) k_check_ball(PassArgs a, int32_t check
     }
 }
 
+// The same check on the failed list with kCheckGroup lanes per particle:
+// one lane's scan of the stencil is a chain of some fifty dependent global
+// loads, so the lanes of a group split the candidates (the same exact test
+// as check_ball_one; any lane's hit sets the flag).
+constexpr int kCheckGroup = 8;
+
+template <int DIM, bool POLY>
+__global__ void __launch_bounds__(kBlock) k_check_ball_group(PassArgs a, Counters *cnt)
+{
+    const int32_t count = a.failed[0];
+    const int sub = threadIdx.x & (kCheckGroup - 1);
+    const int32_t groups = (int32_t)(gridDim.x * blockDim.x / kCheckGroup);
+    const double *__restrict__ X = a.buf.x[0];
+    const double *__restrict__ Y = a.buf.x[1];
+    const double *__restrict__ Z = a.buf.x[2];
+    for (int32_t i = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) / kCheckGroup); i < count;
+         i += groups) {
+        const int32_t p = a.failed[1 + i];
+        const double x = X[p], y = Y[p];
+        const double z = (DIM == 3) ? Z[p] : 0.0;
+        const int32_t cx = cell_coord(x, a.g.inv_w[0], a.g.na[0]);
+        const int32_t cy = cell_coord(y, a.g.inv_w[1], a.g.na[1]);
+        const int32_t cz = (DIM == 3) ? cell_coord(z, a.g.inv_w[2], a.g.na[2]) : 0;
+        int32_t lo[Rows<DIM>::kRanges], hi[Rows<DIM>::kRanges];
+        stencil_slices<DIM>(a.g, a.start, cx, cy, cz, lo, hi);
+        const double Ri = POLY ? a.s * a.buf.rho[p] : a.s;
+        bool hit = false;
+#pragma unroll
+        for (int r = 0; r < Rows<DIM>::kRanges; ++r) {
+            for (int32_t q = lo[r] + sub; q < hi[r] && !hit; q += kCheckGroup) {
+                if (q == p) continue;
+                const double dx = min_image(x - X[q], a.g.box[0], a.g.half[0]);
+                const double dy = min_image(y - Y[q], a.g.box[1], a.g.half[1]);
+                double qq = dx * dx + dy * dy;
+                if (DIM == 3) {
+                    const double dz = min_image(z - Z[q], a.g.box[2], a.g.half[2]);
+                    qq = qq + dz * dz;
+                }
+                double sig2;
+                if (POLY) {
+                    const double sig = Ri + a.s * a.buf.rho[q];
+                    sig2 = sig * sig;
+                } else {
+                    sig2 = a.sig2_mono;
+                }
+                hit = qq <= sig2;
+            }
+        }
+        if (hit) atomicOr(&cnt->overlap, 1);
+    }
+}
+
 
 // ---------------------------------------------------------------- platelets
 
@@ -1339,6 +1391,14 @@ hipError_t check_overlaps(int dim, int shape, bool poly, const PassArgs &a, bool
     if (shape == SRM_PLATELET) {
         if (a.tau != 0.0) hipLaunchKernelGGL(k_check_platelet<true>, grid, block, 0, stream, a, all, cnt);
         else hipLaunchKernelGGL(k_check_platelet<false>, grid, block, 0, stream, a, all, cnt);
+    } else if (!check_all) {
+        if (dim == 3) {
+            if (poly) hipLaunchKernelGGL((k_check_ball_group<3, true>), grid, block, 0, stream, a, cnt);
+            else hipLaunchKernelGGL((k_check_ball_group<3, false>), grid, block, 0, stream, a, cnt);
+        } else {
+            if (poly) hipLaunchKernelGGL((k_check_ball_group<2, true>), grid, block, 0, stream, a, cnt);
+            else hipLaunchKernelGGL((k_check_ball_group<2, false>), grid, block, 0, stream, a, cnt);
+        }
     } else if (dim == 3) {
         if (poly) hipLaunchKernelGGL((k_check_ball<3, true>), grid, block, 0, stream, a, all, cnt);
         else hipLaunchKernelGGL((k_check_ball<3, false>), grid, block, 0, stream, a, all, cnt);
