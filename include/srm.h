@@ -340,7 +340,8 @@ srm_status srm_softrdf_forward_static(const srm_softrdf_params *p, int64_t n,
 typedef struct srm_batch srm_batch;
 
 typedef struct {
-    int64_t replays;        /* graph replays of this run */
+    int64_t replays;        /* graph replays of this run (up to 3 queued after the last
+                               RVE finished, which change nothing) */
     int64_t slots;          /* pass slots (replays * slots per replay) */
     int32_t converged;      /* RVEs at their target */
     int32_t not_converged;  /* RVEs that used up max_sweeps */
@@ -358,7 +359,9 @@ srm_status srm_batch_init(int32_t count, const srm_params *params, const double 
 srm_status srm_batch_configure(srm_batch *b, int32_t slots_per_replay, int32_t block,
                                int32_t wave_occupancy);
 /* Run until every RVE converged or used max_sweeps more sweeps
- * (SRM_ENOTCONV then; converged RVEs keep their result). */
+ * (SRM_ENOTCONV then; converged RVEs keep their result).  Replays are
+ * queued four ahead of the host's check of the unfinished count, so the
+ * device does not wait on the host between replays. */
 srm_status srm_batch_run(srm_batch *b, int32_t max_sweeps, srm_batch_info *info);
 /* Committed state of RVE r: pos (dim*n, host, id order), s, sweep counter,
  * passes run so far (all nullable). */

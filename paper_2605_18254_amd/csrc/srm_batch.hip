@@ -404,6 +404,9 @@ inline unsigned nblk(int64_t n, int b = kB)
 
 }  // namespace
 
+// Graph replays kept in flight by srm_batch_run.
+constexpr int kDepth = 4;
+
 // Host-side record of a batch (opaque through the C ABI).
 struct BatchHost {
     BatchDev d{};
@@ -415,7 +418,8 @@ struct BatchHost {
     int32_t block = kB;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int32_t *hrem = nullptr;    // pinned
+    int32_t *hrem = nullptr;    // pinned, one count per replay in flight
+    hipEvent_t done[kDepth] = {};  // recorded after each replay's count copy
     std::vector<void *> allocs;
 };
 
@@ -572,6 +576,8 @@ srm_status srm_batch_init(int32_t count, const srm_params *params, const double 
     auto bail = [&](srm_status st) {
         for (void *v : h->allocs) (void)hipFree(v);
         if (h->hrem) (void)hipHostFree(h->hrem);
+        for (hipEvent_t ev : h->done)
+            if (ev) (void)hipEventDestroy(ev);
         if (h->stream) (void)hipStreamDestroy(h->stream);
         delete b;
         return st;
@@ -603,8 +609,12 @@ srm_status srm_batch_init(int32_t count, const srm_params *params, const double 
     if (!e) e = balloc(h, &d.prefix, (size_t)32 * (count + 1));
     if (!e) e = balloc(h, &d.remaining, 1);
     if (e) return bail(bfail(SRM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
-    if (hipHostMalloc((void **)&h->hrem, sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void **)&h->hrem, sizeof(int32_t) * kDepth, hipHostMallocDefault) !=
+        hipSuccess)
         return bail(bfail(SRM_ENOMEM, "pinned allocation failed"));
+    for (hipEvent_t &ev : h->done)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+            return bail(bfail(SRM_EDEVICE, "event"));
 
     // control records, particle -> RVE maps, initial P in set 0 (id order,
     // binned by the first pass slot of each sweep)
@@ -706,15 +716,29 @@ srm_status srm_batch_run(srm_batch *b, int32_t max_sweeps, srm_batch_info *info)
     }
     BHIP(hipMemcpy(h->d.rve, cur.data(), sizeof(Rve) * h->d.count, hipMemcpyHostToDevice));
     if (!h->exec) BHIP(build_graph(h));
-    int64_t replays = 0;
-    for (;;) {
-        BHIP(hipGraphLaunch(h->exec, h->stream));
-        BHIP(hipMemcpyAsync(h->hrem, h->d.remaining, sizeof(int32_t), hipMemcpyDeviceToHost,
-                            h->stream));
-        BHIP(hipStreamSynchronize(h->stream));
-        ++replays;
-        if (*h->hrem == 0) break;
+    // Up to kDepth replays are queued ahead, each followed by a copy of its
+    // count of unfinished RVEs into its own pinned slot and an event.  The
+    // host waits for the oldest replay only, so the device never idles on
+    // the host's check; once a count reads 0 nothing more is queued.  A
+    // replay after the last RVE finished changes nothing (every RVE is
+    // inactive), so the few already queued behind it are harmless.
+    int64_t replays = 0, retired = 0;
+    bool finished = false;
+    while (!finished) {
+        while (replays - retired < kDepth) {
+            const int slot = (int)(replays % kDepth);
+            BHIP(hipGraphLaunch(h->exec, h->stream));
+            BHIP(hipMemcpyAsync(h->hrem + slot, h->d.remaining, sizeof(int32_t),
+                                hipMemcpyDeviceToHost, h->stream));
+            BHIP(hipEventRecord(h->done[slot], h->stream));
+            ++replays;
+        }
+        const int slot = (int)(retired % kDepth);
+        BHIP(hipEventSynchronize(h->done[slot]));
+        finished = h->hrem[slot] == 0;
+        ++retired;
     }
+    BHIP(hipStreamSynchronize(h->stream));
     BHIP(hipMemcpy(cur.data(), h->d.rve, sizeof(Rve) * h->d.count, hipMemcpyDeviceToHost));
     int32_t done = 0, notconv = 0;
     int64_t passes = 0, updates = 0;
@@ -768,6 +792,8 @@ srm_status srm_batch_free(srm_batch *b)
     if (h->graph) (void)hipGraphDestroy(h->graph);
     for (void *v : h->allocs) (void)hipFree(v);
     if (h->hrem) (void)hipHostFree(h->hrem);
+    for (hipEvent_t ev : h->done)
+        if (ev) (void)hipEventDestroy(ev);
     (void)hipStreamDestroy(h->stream);
     delete b;
     return SRM_OK;
