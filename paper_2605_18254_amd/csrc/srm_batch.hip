@@ -172,20 +172,66 @@ __global__ void k_ctl_begin(BatchDev d)
 
 // Prefix sums over RVEs of the colour cells of each class (dimension, one
 // thread or one wavefront per cell) and colour.
-__global__ void k_ctl_prefix(BatchDev d)
+// Exclusive prefix over the RVEs of their colour-cell counts, one list per
+// (class, colour) j = class * 8 + colour (class: 2D/3D x thread/wavefront per
+// cell), counting only active RVEs of that class.  One thread per RVE, 256
+// RVEs a chunk, a wavefront scan per list.
+constexpr int kCtlBlock = 256;
+
+__global__ void __launch_bounds__(kCtlBlock) k_ctl_prefix(BatchDev d)
 {
-    const int j = threadIdx.x;  // class * 8 + colour
-    if (j >= 32) return;
-    const int cls = j >> 3, colour = j & 7;
-    const int dim = (cls >> 1) ? 3 : 2, wave = cls & 1;
-    int32_t *pre = d.prefix + (size_t)j * (d.count + 1);
-    int32_t run = 0;
-    for (int32_t i = 0; i < d.count; ++i) {
-        pre[i] = run;
-        const Rve &r = d.rve[i];
-        if (r.active && r.dim == dim && r.wave == wave) run += r.ccount[colour];
+    __shared__ int32_t wtot[32][kCtlBlock / 64];
+    __shared__ int32_t carry[32];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid < 32) carry[tid] = 0;
+    __syncthreads();
+    for (int32_t base = 0; base < d.count; base += kCtlBlock) {
+        const int32_t i = base + tid;
+        bool act = false;
+        int32_t dim = 0, wave = 0, cc[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) cc[c] = 0;
+        if (i < d.count) {
+            const Rve &r = d.rve[i];
+            act = r.active != 0;
+            dim = r.dim;
+            wave = r.wave;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) cc[c] = r.ccount[c];
+        }
+        int32_t v[32], incl[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const int cls = j >> 3;
+            const bool m = act && dim == ((cls >> 1) ? 3 : 2) && wave == (cls & 1);
+            v[j] = m ? cc[j & 7] : 0;
+            int32_t x = v[j];
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t u = __shfl_up(x, o, 64);
+                if (lane >= o) x += u;
+            }
+            incl[j] = x;
+        }
+        if (lane == 63)
+#pragma unroll
+            for (int j = 0; j < 32; ++j) wtot[j][wv] = incl[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            int32_t off = carry[j];
+            for (int w = 0; w < wv; ++w) off += wtot[j][w];
+            if (i < d.count) d.prefix[(size_t)j * (d.count + 1) + i] = off + incl[j] - v[j];
+        }
+        __syncthreads();
+        if (tid < 32) {
+            int32_t t = 0;
+            for (int w = 0; w < kCtlBlock / 64; ++w) t += wtot[tid][w];
+            carry[tid] += t;
+        }
+        __syncthreads();
     }
-    pre[d.count] = run;
+    if (tid < 32) d.prefix[(size_t)tid * (d.count + 1) + d.count] = carry[tid];
 }
 
 __global__ void k_ctl_end(BatchDev d)
@@ -469,7 +515,7 @@ hipError_t enqueue_slot(BatchHost *h)
     hipStream_t s = h->stream;
     const unsigned rb = nblk(d.count, 64);
     hipLaunchKernelGGL(k_ctl_begin, dim3(rb), dim3(64), 0, s, d);
-    hipLaunchKernelGGL(k_ctl_prefix, dim3(1), dim3(64), 0, s, d);
+    hipLaunchKernelGGL(k_ctl_prefix, dim3(1), dim3(kCtlBlock), 0, s, d);
     // Algorithm 2 for every active RVE: counting sort src -> dst
     hipLaunchKernelGGL(k_bfill, dim3(nblk(d.ncells)), dim3(kB), 0, s, d);
     hipLaunchKernelGGL(k_bcount, dim3(nblk(d.ntotal)), dim3(kB), 0, s, d);
