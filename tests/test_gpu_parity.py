@@ -219,6 +219,61 @@ def test_tile_trial_counts_bitexact(srm, oracle_lib, n_l):
     g.close()
 
 
+def _region_loads(counts, nt, span=9):
+    """Particles in each tile's (span)^3-cell region, every colour: a tile
+    covers 4 colour cells (8 cells) per axis, its region starts one cell
+    below its first cell of the colour."""
+    na = counts.shape[0]
+    loads = []
+    for colour in range(8):
+        off = [(colour >> a) & 1 for a in range(3)]
+        for tz in range(nt):
+            for ty in range(nt):
+                for tx in range(nt):
+                    idx = [(np.arange(span) + 8 * t + o - 1) % na
+                           for t, o in zip((tx, ty, tz), off)]
+                    loads.append(int(counts[np.ix_(idx[0], idx[1], idx[2])].sum()))
+    return np.array(loads)
+
+
+def test_tile_over_capacity_bitexact(srm, oracle_lib):
+    """A dense slab (f = 0.45 in the lower half of the box) and an empty upper
+    half: the mean load picks the standard LDS tile, but tens of tiles inside
+    the slab hold more particles than its capacity and go to the
+    global-memory kernel in the same colour phase.  Six sweeps without
+    swelling equal the oracle, accept codes included."""
+    slab = srm_inputs.make("spheres3d", n=6700, seed=91, f_target=0.45, box=(1.0, 1.0, 0.5),
+                           c_w=0.03)
+    o_slab = oracle_lib.Oracle.from_workload(slab)
+    o_slab.run(400)
+    s = o_slab.s
+    assert s == slab.s_target
+    w = srm_inputs.make("spheres3d", n=6700, seed=91, f_target=0.225, c_w=0.0)
+    over = dict(pos=o_slab.soa(), s0=s, sweep0=o_slab.t, s_target=s, c_m=slab.c_m)
+    o = oracle_lib.Oracle.from_workload(w, **over)
+    g = srm.SRM.from_workload(w, **over)
+    # the case this test is for: over-capacity tiles under the standard tile
+    na, inv = o.grid_for_scale(s)
+    assert int(na[0]) == int(na[1]) == int(na[2]) >= 9
+    cells = o.bin(na, inv)
+    counts = np.bincount(cells, minlength=int(np.prod(na))).reshape(
+        int(na[2]), int(na[1]), int(na[0])).transpose(2, 1, 0)
+    cap = 1456
+    assert w.n / np.prod(na) * 729 <= cap - 3 * math.sqrt(cap)
+    loads = _region_loads(counts, (int(na[0]) // 2 + 3) // 4)
+    _say(f"over-capacity test: grid {na}, region loads max {loads.max()}, "
+         f"over {int((loads > cap).sum())}")
+    assert (loads > cap).sum() >= 10
+    for k in range(6):
+        io, acc_o = o.sweep()
+        ig = g.sweep()
+        assert ig["committed"] == io["committed"], k
+        assert ig["passes_main"] == io["passes_main"], k
+        assert np.array_equal(g.last_acc(), acc_o), k
+        _assert_same_state(g, o, f"sweep {k}")
+    g.close()
+
+
 @pytest.mark.parametrize("dim,n,box,f", [(3, 20000, (1.0, 0.6, 1.5), 0.35),
                                          (2, 4000, (1.0, 2.5), 0.5)])
 def test_stretched_box_bitexact(srm, oracle_lib, dim, n, box, f):
