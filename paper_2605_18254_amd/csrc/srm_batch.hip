@@ -34,6 +34,15 @@ namespace srm {
 namespace {
 
 constexpr int kB = 256;
+// Lanes per colour cell of a sparse-grid launch, and cells per wavefront:
+// a 3D stencil holds 27 cells, a 2D one 9 (of 1, 2, 4 and 8 lanes, two
+// were fastest in 2D).
+template <int DIM>
+struct Sparse {
+    static constexpr int kGroup = (DIM == 3) ? 8 : 2;
+    static constexpr int kCells = 64 / kGroup;
+    static_assert(64 % kGroup == 0, "a group stays inside one wavefront");
+};
 constexpr int32_t kWaveGrid = 8192;  // workgroups of a wavefront-per-cell launch
 
 enum : int32_t { kSweepStart = 0, kMain = 1, kShake = 2, kDone = 3, kNotConv = 4 };
@@ -170,12 +179,12 @@ __global__ void k_ctl_begin(BatchDev d)
     r.active = 1;
 }
 
-// Prefix sums over RVEs of the colour cells of each class (dimension, one
-// thread or one wavefront per cell) and colour.
-// Exclusive prefix over the RVEs of their colour-cell counts, one list per
-// (class, colour) j = class * 8 + colour (class: 2D/3D x thread/wavefront per
-// cell), counting only active RVEs of that class.  One thread per RVE, 256
-// RVEs a chunk, a wavefront scan per list.
+// Exclusive prefix over the RVEs of their work units, one list per (class,
+// colour) j = class * 8 + colour (class: 2D/3D x sparse/crowded grid),
+// counting only active RVEs of that class.  A crowded grid's unit is a
+// colour cell (one wavefront each), a sparse grid's a wavefront's worth of
+// Sparse<dim>::kCells colour cells.  One thread per RVE, 256 RVEs a chunk, a
+// wavefront scan per list.
 constexpr int kCtlBlock = 256;
 
 __global__ void __launch_bounds__(kCtlBlock) k_ctl_prefix(BatchDev d)
@@ -204,7 +213,9 @@ __global__ void __launch_bounds__(kCtlBlock) k_ctl_prefix(BatchDev d)
         for (int j = 0; j < 32; ++j) {
             const int cls = j >> 3;
             const bool m = act && dim == ((cls >> 1) ? 3 : 2) && wave == (cls & 1);
-            v[j] = m ? cc[j & 7] : 0;
+            // sparse-grid classes count wavefronts of Sparse<dim>::kCells cells
+            const int cpw = (cls >> 1) ? Sparse<3>::kCells : Sparse<2>::kCells;
+            v[j] = !m ? 0 : (cls & 1) ? cc[j & 7] : (cc[j & 7] + cpw - 1) / cpw;
             int32_t x = v[j];
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
@@ -366,21 +377,34 @@ __global__ void __launch_bounds__(kB) k_brank(BatchDev d)
     if (r.poly) d.rho[t][q] = d.rho[s][p];
 }
 
-// One thread per colour cell of every active RVE of dimension DIM.
+// Sparse<DIM>::kGroup lanes per colour cell of every active RVE of
+// dimension DIM whose grid is sparse; a wavefront takes Sparse<DIM>::kCells
+// cells of one RVE, so the RVE's record is read once per wavefront.  The
+// cell's particles are still taken one at a time in ascending id order and
+// each one's trials in order (Algorithm 3); the group's lanes split a
+// trial's stencil (every kGroup-th candidate of each slice) and the trial
+// is accepted when none of them finds a contact (Algorithm 5, the same FP64
+// test as the single-box kernels).  Every lane of the group stores the
+// accepted position, so each lane's later reads of that slot follow its own
+// store.
 template <int DIM, bool POLY>
 __global__ void __launch_bounds__(kB) k_bmigrate(BatchDev d, int colour)
 {
+    constexpr int kGroup = Sparse<DIM>::kGroup;
     const int32_t *pre = d.prefix + (size_t)((DIM == 3 ? 16 : 0) + colour) * (d.count + 1);
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= pre[d.count]) return;
-    int32_t lo = 0, hi = d.count - 1;  // last RVE with pre[i] <= t
+    const int32_t w = __builtin_amdgcn_readfirstlane((int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const int lane = threadIdx.x & 63;
+    const int32_t sub = lane % kGroup;
+    if (w >= pre[d.count]) return;  // wavefront-uniform
+    int32_t lo = 0, hi = d.count - 1;  // last RVE with pre[i] <= w
     while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= t) lo = mid;
+        if (pre[mid] <= w) lo = mid;
         else hi = mid - 1;
     }
     const Rve &r = d.rve[lo];
-    const int32_t u = t - pre[lo];
+    const int32_t u = (w - pre[lo]) * Sparse<DIM>::kCells + lane / kGroup;
+    if (u >= r.ccount[colour]) return;  // group-uniform
     int32_t h[3], off[3];
     for (int ax = 0; ax < 3; ++ax) {
         const bool split = ax < DIM && r.g.na[ax] >= 4;
@@ -389,8 +413,47 @@ __global__ void __launch_bounds__(kB) k_bmigrate(BatchDev d, int colour)
     }
     const int32_t jx = u % h[0], jy = (u / h[0]) % h[1], jz = u / (h[0] * h[1]);
     const PassArgs a = pass_args_of(d, r);
-    migrate_cell_global<DIM, POLY>(a, 2 * jx + off[0], 2 * jy + off[1],
-                                   (DIM == 3) ? 2 * jz + off[2] : 0);
+    const int32_t cx = 2 * jx + off[0], cy = 2 * jy + off[1], cz = (DIM == 3) ? 2 * jz + off[2] : 0;
+    const int32_t c = cx + a.g.na[0] * (cy + a.g.na[1] * cz);
+    const int32_t beg = a.start[c], end = a.start[c + 1];
+    if (beg == end) return;  // group-uniform
+    int32_t slo[Rows<DIM>::kRanges], shi[Rows<DIM>::kRanges];
+    stencil_slices<DIM>(a.g, a.start, cx, cy, cz, slo, shi);
+    const unsigned long long gmask = ((1ull << kGroup) - 1) << ((threadIdx.x & 63) & ~(kGroup - 1));
+    double *__restrict__ X = a.buf.x[0];
+    double *__restrict__ Y = a.buf.x[1];
+    double *__restrict__ Z = a.buf.x[2];
+    for (int32_t p = beg; p < end; ++p) {
+        const double ox = X[p], oy = Y[p], oz = (DIM == 3) ? Z[p] : 0.0;
+        const uint32_t id = (uint32_t)a.buf.id[p];
+        const double Ri = POLY ? a.s * a.buf.rho[p] : a.s;
+        int32_t code = 0;
+        for (int32_t l = 1; l <= a.n_l; ++l) {
+            double yx, yy, yz;
+            wave_trial<DIM>(a, id, l, ox, oy, oz, yx, yy, yz);
+            bool hit = false;
+#pragma unroll 1  // unrolled, each slice's loop is pipelined apart: 255 VGPRs
+            for (int k = 0; k < Rows<DIM>::kRanges; ++k) {
+                for (int32_t q = slo[k] + sub; q < shi[k] && !hit; q += kGroup) {
+                    if (q == p) continue;
+                    hit = wave_hit<DIM, POLY>(a, yx, yy, yz, Ri, X[q], Y[q],
+                                              (DIM == 3) ? Z[q] : 0.0,
+                                              POLY ? a.s * a.buf.rho[q] : a.s);
+                }
+            }
+            if ((__ballot(hit) & gmask) == 0) {
+                X[p] = yx;
+                Y[p] = yy;
+                if (DIM == 3) Z[p] = yz;
+                code = l;
+                break;
+            }
+        }
+        if (sub == 0) {
+            a.acc[p] = (uint8_t)code;
+            if (code == 0) a.failed[1 + atomicAdd(&a.failed[0], 1)] = p;
+        }
+    }
 }
 
 // One 64-thread workgroup per colour cell of every active RVE of dimension
@@ -528,10 +591,12 @@ hipError_t enqueue_slot(BatchHost *h)
     for (int dc = 0; dc < 2; ++dc) {
         const int dim = dc ? 3 : 2;
         if (h->bound[dc] == 0) continue;
-        const dim3 grid(nblk(h->bound[dc], h->block)), block(h->block);
+        // sparse grids: at most ccount / kCells + 1 wavefronts an RVE
+        const int64_t waves = h->bound[dc] / (dc ? Sparse<3>::kCells : Sparse<2>::kCells) + d.count;
+        const dim3 grid(nblk(waves * 64, h->block)), block(h->block);
         const dim3 wgrid(h->bound[dc] < kWaveGrid ? h->bound[dc] : kWaveGrid), wblock(64);
         for (int colour = 0; colour < (1 << dim); ++colour) {
-            // sparse grids: a thread per cell; crowded grids: a wavefront per cell
+            // sparse grids: a lane group per cell; crowded grids: a wavefront per cell
             if (dim == 3) {
                 if (h->poly) {
                     hipLaunchKernelGGL((k_bmigrate<3, true>), grid, block, 0, s, d, colour);
@@ -736,7 +801,7 @@ srm_status srm_batch_configure(srm_batch *b, int32_t slots_per_replay, int32_t b
                                int32_t wave_occupancy)
 {
     if (!b || slots_per_replay < 1 || slots_per_replay > 64 ||
-        (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024) ||
+        (block != 64 && block != 128 && block != 256) ||
         wave_occupancy < 1 || wave_occupancy > 64)
         return bfail(SRM_EINVAL, "bad configuration");
     b->h.slots = slots_per_replay;

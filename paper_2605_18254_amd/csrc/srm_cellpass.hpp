@@ -270,6 +270,64 @@ __device__ __forceinline__ bool wave_ref_hit(const PassArgs &a, const WaveLds &L
                                POLY ? a.s * a.buf.rho[ref] : a.s);
 }
 
+// Algorithm 3 for the particles of one cell, G consecutive lanes of a
+// wavefront per cell (G divides 64; the G lanes call it uniformly).  The
+// particles are still taken one at a time in ascending id order and each
+// one's trials in order; the lanes split a trial's stencil (every G-th
+// candidate of each slice), and the trial is accepted when none of them
+// finds a contact (Algorithm 5, the test of ball_hits).  Every lane of the
+// group stores the accepted position, so each lane's later reads of that
+// slot follow its own store.
+template <int DIM, bool POLY, int G>
+__device__ __forceinline__ void migrate_cell_lanes(const PassArgs &a, int32_t cx, int32_t cy,
+                                                   int32_t cz)
+{
+    static_assert(64 % G == 0, "a group stays inside one wavefront");
+    const int lane = threadIdx.x & 63;
+    const int32_t sub = lane % G;
+    const int32_t c = cx + a.g.na[0] * (cy + a.g.na[1] * cz);
+    const int32_t beg = a.start[c], end = a.start[c + 1];
+    if (beg == end) return;  // group-uniform
+    int32_t slo[Rows<DIM>::kRanges], shi[Rows<DIM>::kRanges];
+    stencil_slices<DIM>(a.g, a.start, cx, cy, cz, slo, shi);
+    constexpr unsigned long long kOnes = (G == 64) ? ~0ull : ((1ull << (G % 64)) - 1);
+    const unsigned long long gmask = kOnes << (lane & ~(G - 1));
+    double *__restrict__ X = a.buf.x[0];
+    double *__restrict__ Y = a.buf.x[1];
+    double *__restrict__ Z = a.buf.x[2];
+    for (int32_t p = beg; p < end; ++p) {
+        const double ox = X[p], oy = Y[p], oz = (DIM == 3) ? Z[p] : 0.0;
+        const uint32_t id = (uint32_t)a.buf.id[p];
+        const double Ri = POLY ? a.s * a.buf.rho[p] : a.s;
+        int32_t code = 0;
+        for (int32_t l = 1; l <= a.n_l; ++l) {
+            double yx, yy, yz;
+            wave_trial<DIM>(a, id, l, ox, oy, oz, yx, yy, yz);
+            bool hit = false;
+#pragma unroll 1  // unrolled, each slice's loop is pipelined apart (255 VGPRs)
+            for (int k = 0; k < Rows<DIM>::kRanges; ++k) {
+                for (int32_t q = slo[k] + sub; q < shi[k] && !hit; q += G) {
+                    if (q == p) continue;
+                    hit = wave_hit<DIM, POLY>(a, yx, yy, yz, Ri, X[q], Y[q],
+                                              (DIM == 3) ? Z[q] : 0.0,
+                                              POLY ? a.s * a.buf.rho[q] : a.s);
+                }
+            }
+            if ((__ballot(hit) & gmask) == 0) {
+                X[p] = yx;
+                Y[p] = yy;
+                if (DIM == 3) Z[p] = yz;
+                code = l;
+                break;
+            }
+        }
+        if (sub == 0) {
+            a.acc[p] = (uint8_t)code;
+            if (code == 0) a.failed[1 + atomicAdd(&a.failed[0], 1)] = p;
+        }
+    }
+}
+
 // Must be called by all 64 threads of a 64-thread workgroup, uniformly.
 template <int DIM, bool POLY>
 __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int32_t cz,
@@ -280,8 +338,8 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
     const int32_t beg = a.start[c], end = a.start[c + 1];
     const int32_t cnt = end - beg;
     if (cnt == 0) return;
-    if (cnt > kWaveOwn) {
-        if (lane == 0) migrate_cell_global<DIM, POLY>(a, cx, cy, cz);
+    if (cnt > kWaveOwn) {  // beyond LDS: the stencil split over the lanes
+        migrate_cell_lanes<DIM, POLY, 64>(a, cx, cy, cz);
         return;
     }
     const double *__restrict__ X = a.buf.x[0];

@@ -189,6 +189,38 @@ def test_crowded_cells_bitexact(srm, oracle_lib, dim, n, seed, f, sigma):
     g.close()
 
 
+@pytest.mark.parametrize("dim,n,big,c_m_rel", [(3, 1500, 8.0, 0.3), (2, 2000, 24.0, 0.5)])
+def test_cells_beyond_wave_capacity_bitexact(srm, oracle_lib, dim, n, big, c_m_rel):
+    """One particle of 8 (3D) or 24 (2D) times the others' radius sets a cell
+    edge of many small diameters, so the grid ends as one cell holding every
+    particle.  Cells beyond the wavefront kernel's 96 LDS slots split each
+    trial's stencil over the wavefront's lanes; every sweep equals the
+    oracle, and most sweeps run such cells."""
+    import dataclasses
+    w = _mk(dim, n, 80 + dim, 0.3)
+    rho = np.ones(n)
+    rho[n // 2] = big
+    s_t = srm_inputs.target_scale(dim, srm_inputs.BALL, 0.3, w.box, rho, n)
+    w = dataclasses.replace(w, rho=rho, s_target=s_t, c_m=c_m_rel * s_t)
+    o = oracle_lib.Oracle.from_workload(w)
+    g = srm.SRM.from_workload(w)
+    sweeps = beyond = 0
+    while o.s < w.s_target:
+        io, acc_o = o.sweep()
+        ig = g.sweep()
+        sweeps += 1
+        assert ig["committed"] == io["committed"] and tuple(ig["grid"]) == tuple(
+            int(x) for x in io["na"]), sweeps
+        beyond += n > 96 * int(np.prod(ig["grid"][:dim]))
+        if sweeps % 5 == 0:
+            assert np.array_equal(g.last_acc(), acc_o), sweeps
+            _assert_same_state(g, o, f"sweep {sweeps}")
+    _assert_same_state(g, o, "final")
+    assert beyond >= 40, beyond
+    _say(f"{dim}D, one particle {big}x: {sweeps} sweeps, {beyond} with cells beyond 96")
+    g.close()
+
+
 @pytest.mark.parametrize("sigma,seed,f,bits", [(None, 71, 0.35, 1 | 32),
                                                (0.05, 5, 0.25, 1 | 32 | 16 | 2)])
 def test_tile_variants_bitexact(srm, oracle_lib, sigma, seed, f, bits):
