@@ -183,7 +183,7 @@ __device__ __forceinline__ bool check_ball_wave(const PassArgs &a, int32_t p, in
 // against the whole stencil; a cell with more than kWaveOwn particles runs
 // on one lane with the global-memory routine above.
 constexpr int kWaveOwn = 96;
-constexpr int kWaveNear = 32;
+constexpr int kWaveNear = 24;
 constexpr int kWaveOccupancy = 3;  // mean particles per cell that selects this path
 
 struct WaveOwn {
