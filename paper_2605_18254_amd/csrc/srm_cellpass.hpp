@@ -413,6 +413,7 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
     auto pair_pass = [&](int32_t q) {
         const float qx = (float)X[q], qy = (float)Y[q], qz = (DIM == 3) ? (float)Z[q] : 0.0f;
         const float Rq = (float)(POLY ? a.s * a.buf.rho[q] : a.s);
+#pragma unroll 4  // independent list appends of four own particles overlap
         for (int32_t k = 0; k < cnt; ++k) {
             const float4 o = L.own32[k];
             if (near32(o, qx, qy, qz, (o.w + Rq) + cm2)) {
@@ -469,6 +470,7 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
     if (lane < nk) pair_pass(L.kept[lane]);
     for (int32_t j = lane; j < cnt; j += 64) {
         const float4 b = L.own32[j];
+#pragma unroll 4  // independent list appends of four own particles overlap
         for (int32_t k = 0; k < cnt; ++k) {
             if (k == j) continue;
             const float4 o = L.own32[k];
