@@ -352,8 +352,8 @@ typedef struct {
 srm_status srm_batch_init(int32_t count, const srm_params *params, const double *pos,
                           const double *rho, srm_batch **out);
 /* Schedule only (results do not depend on it): pass slots per graph replay
- * (1..64), threads per block of the sparse-grid migration kernels (64,
- * 128 or 256; eight lanes share a cell there), and the mean particles per
+ * (1..64), threads per block of the sparse-grid migration kernels (64, 128
+ * or 256; a group of lanes shares a cell there), and the mean particles per
  * cell (1..64, default 3) from which an RVE's grid migrates with one
  * wavefront per cell instead. */
 srm_status srm_batch_configure(srm_batch *b, int32_t slots_per_replay, int32_t block,

@@ -83,7 +83,7 @@ class Batch:
 
     def configure(self, slots: int, block: int, wave_occupancy: int = 3):
         """Schedule: pass slots per graph replay, threads per block of the
-        sparse-grid kernels (eight lanes a cell), and the occupancy from
+        sparse-grid kernels (a group of lanes a cell), and the occupancy from
         which a grid is migrated with one wavefront per cell."""
         _bcheck(_bind().srm_batch_configure(self._ctx, int(slots), int(block),
                                             int(wave_occupancy)))

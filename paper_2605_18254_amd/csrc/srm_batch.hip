@@ -34,12 +34,12 @@ namespace srm {
 namespace {
 
 constexpr int kB = 256;
-// Lanes per colour cell of a sparse-grid launch, and cells per wavefront:
-// a 3D stencil holds 27 cells, a 2D one 9 (of 1, 2, 4 and 8 lanes, two
-// were fastest in 2D).
+// Lanes per colour cell of a sparse-grid launch, and cells per wavefront
+// (the fastest of 2 to 16 lanes in 3D and of 1 to 8 in 2D, timed on the
+// 256-RVE ensemble).
 template <int DIM>
 struct Sparse {
-    static constexpr int kGroup = (DIM == 3) ? 8 : 2;
+    static constexpr int kGroup = (DIM == 3) ? 4 : 2;
     static constexpr int kCells = 64 / kGroup;
     static_assert(64 % kGroup == 0, "a group stays inside one wavefront");
 };
