@@ -715,6 +715,25 @@ def test_batch_members_bitidentical_to_solo_runs(srm, oracle_lib):
     b.close()
 
 
+def test_batch_configure_rejects_bad_shapes(srm):
+    """Pass slots 1..64, blocks of 64, 128 or 256 threads (whole wavefronts
+    of lane groups, within the kernels' launch bounds) and a crowded
+    threshold of 1..64 particles a cell; anything else is refused before a
+    graph is built, and the ensemble still runs after."""
+    from paper_2605_18254_amd.batch import Batch
+    metas = srm_inputs.batch_members(count=2, n_scale=0.01, seed0=2100)
+    ws = [srm_inputs.make_member(m) for m in metas]
+    b = Batch(ws)
+    for bad in [(0, 128, 3), (65, 128, 3), (2, 32, 3), (2, 96, 3), (2, 512, 3),
+                (2, 1024, 3), (2, 128, 0), (2, 128, 65)]:
+        with pytest.raises(srm.SrmError):
+            b.configure(*bad)
+    b.configure(2, 64, 3)
+    st, info = b.run(600)
+    assert st == 0 and info["converged"] == len(ws)
+    b.close()
+
+
 def test_batch_launch_shape_invariance_and_notconv(srm):
     from paper_2605_18254_amd.batch import Batch
     metas = srm_inputs.batch_members(count=6, n_scale=0.03, seed0=2000)
