@@ -380,13 +380,8 @@ __global__ void __launch_bounds__(kB) k_brank(BatchDev d)
 // Sparse<DIM>::kGroup lanes per colour cell of every active RVE of
 // dimension DIM whose grid is sparse; a wavefront takes Sparse<DIM>::kCells
 // cells of one RVE, so the RVE's record is read once per wavefront.  The
-// cell's particles are still taken one at a time in ascending id order and
-// each one's trials in order (Algorithm 3); the group's lanes split a
-// trial's stencil (every kGroup-th candidate of each slice) and the trial
-// is accepted when none of them finds a contact (Algorithm 5, the same FP64
-// test as the single-box kernels).  Every lane of the group stores the
-// accepted position, so each lane's later reads of that slot follow its own
-// store.
+// group runs Algorithm 3 for its cell with the trial's stencil split over
+// its lanes (migrate_cell_lanes).
 template <int DIM, bool POLY>
 __global__ void __launch_bounds__(kB) k_bmigrate(BatchDev d, int colour)
 {
@@ -394,7 +389,6 @@ __global__ void __launch_bounds__(kB) k_bmigrate(BatchDev d, int colour)
     const int32_t *pre = d.prefix + (size_t)((DIM == 3 ? 16 : 0) + colour) * (d.count + 1);
     const int32_t w = __builtin_amdgcn_readfirstlane((int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     const int lane = threadIdx.x & 63;
-    const int32_t sub = lane % kGroup;
     if (w >= pre[d.count]) return;  // wavefront-uniform
     int32_t lo = 0, hi = d.count - 1;  // last RVE with pre[i] <= w
     while (lo < hi) {
@@ -413,47 +407,8 @@ __global__ void __launch_bounds__(kB) k_bmigrate(BatchDev d, int colour)
     }
     const int32_t jx = u % h[0], jy = (u / h[0]) % h[1], jz = u / (h[0] * h[1]);
     const PassArgs a = pass_args_of(d, r);
-    const int32_t cx = 2 * jx + off[0], cy = 2 * jy + off[1], cz = (DIM == 3) ? 2 * jz + off[2] : 0;
-    const int32_t c = cx + a.g.na[0] * (cy + a.g.na[1] * cz);
-    const int32_t beg = a.start[c], end = a.start[c + 1];
-    if (beg == end) return;  // group-uniform
-    int32_t slo[Rows<DIM>::kRanges], shi[Rows<DIM>::kRanges];
-    stencil_slices<DIM>(a.g, a.start, cx, cy, cz, slo, shi);
-    const unsigned long long gmask = ((1ull << kGroup) - 1) << ((threadIdx.x & 63) & ~(kGroup - 1));
-    double *__restrict__ X = a.buf.x[0];
-    double *__restrict__ Y = a.buf.x[1];
-    double *__restrict__ Z = a.buf.x[2];
-    for (int32_t p = beg; p < end; ++p) {
-        const double ox = X[p], oy = Y[p], oz = (DIM == 3) ? Z[p] : 0.0;
-        const uint32_t id = (uint32_t)a.buf.id[p];
-        const double Ri = POLY ? a.s * a.buf.rho[p] : a.s;
-        int32_t code = 0;
-        for (int32_t l = 1; l <= a.n_l; ++l) {
-            double yx, yy, yz;
-            wave_trial<DIM>(a, id, l, ox, oy, oz, yx, yy, yz);
-            bool hit = false;
-#pragma unroll 1  // unrolled, each slice's loop is pipelined apart: 255 VGPRs
-            for (int k = 0; k < Rows<DIM>::kRanges; ++k) {
-                for (int32_t q = slo[k] + sub; q < shi[k] && !hit; q += kGroup) {
-                    if (q == p) continue;
-                    hit = wave_hit<DIM, POLY>(a, yx, yy, yz, Ri, X[q], Y[q],
-                                              (DIM == 3) ? Z[q] : 0.0,
-                                              POLY ? a.s * a.buf.rho[q] : a.s);
-                }
-            }
-            if ((__ballot(hit) & gmask) == 0) {
-                X[p] = yx;
-                Y[p] = yy;
-                if (DIM == 3) Z[p] = yz;
-                code = l;
-                break;
-            }
-        }
-        if (sub == 0) {
-            a.acc[p] = (uint8_t)code;
-            if (code == 0) a.failed[1 + atomicAdd(&a.failed[0], 1)] = p;
-        }
-    }
+    migrate_cell_lanes<DIM, POLY, kGroup>(a, 2 * jx + off[0], 2 * jy + off[1],
+                                          (DIM == 3) ? 2 * jz + off[2] : 0);
 }
 
 // One 64-thread workgroup per colour cell of every active RVE of dimension
