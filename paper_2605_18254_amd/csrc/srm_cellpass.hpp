@@ -410,10 +410,47 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
         const float g = fabsf(d) - hw;
         return g > 0.0f ? g : 0.0f;
     };
+    // With at least four cells on every axis the cell edge is at most L/4
+    // and at least the largest reach, so a candidate within reach of an own
+    // particle lies within 1.5 edges of the cell's centre.  Shifted once to
+    // the image nearest that centre, its difference to every own particle
+    // is then the minimum image whenever it is within reach (and never
+    // smaller otherwise), as is the difference of two own particles: the
+    // pair filters need no per-pair wrap.  The shift adds one rounding of
+    // at most L 2^-24, inside the margin above.
+    const bool direct = a.g.na[0] >= 4 && a.g.na[1] >= 4 && (DIM == 2 || a.g.na[2] >= 4);
+    auto near32d = [&](const float4 &o, float px, float py, float pz, float reach) {
+        const float dx = o.x - px, dy = o.y - py;
+        float qq = dx * dx + dy * dy;
+        if (DIM == 3) {
+            const float dz = o.z - pz;
+            qq = qq + dz * dz;
+        }
+        const float rr = reach * 1.00001f + tol32;
+        return qq <= rr * rr;
+    };
+    auto to_centre = [](float q, float c, float h, float b) {
+        const float d = q - c;
+        return d > h ? q - b : (d < -h ? q + b : q);
+    };
     auto pair_pass = [&](int32_t q) {
-        const float qx = (float)X[q], qy = (float)Y[q], qz = (DIM == 3) ? (float)Z[q] : 0.0f;
+        float qx = (float)X[q], qy = (float)Y[q], qz = (DIM == 3) ? (float)Z[q] : 0.0f;
         const float Rq = (float)(POLY ? a.s * a.buf.rho[q] : a.s);
+        if (direct) {
+            qx = to_centre(qx, ccx, hx32, bx32);
+            qy = to_centre(qy, ccy, hy32, by32);
+            if (DIM == 3) qz = to_centre(qz, ccz, hz32, bz32);
 #pragma unroll 4  // independent list appends of four own particles overlap
+            for (int32_t k = 0; k < cnt; ++k) {
+                const float4 o = L.own32[k];
+                if (near32d(o, qx, qy, qz, (o.w + Rq) + cm2)) {
+                    const int32_t slot = atomicAdd(&L.nn[k], 1);
+                    if (slot < kWaveNear) L.near[k * kWaveNear + slot] = q;
+                }
+            }
+            return;
+        }
+#pragma unroll 4
         for (int32_t k = 0; k < cnt; ++k) {
             const float4 o = L.own32[k];
             if (near32(o, qx, qy, qz, (o.w + Rq) + cm2)) {
@@ -474,7 +511,8 @@ __device__ void migrate_cell_wave(const PassArgs &a, int32_t cx, int32_t cy, int
         for (int32_t k = 0; k < cnt; ++k) {
             if (k == j) continue;
             const float4 o = L.own32[k];
-            if (near32(o, b.x, b.y, b.z, (o.w + b.w) + cm3)) {
+            if (direct ? near32d(o, b.x, b.y, b.z, (o.w + b.w) + cm3)
+                       : near32(o, b.x, b.y, b.z, (o.w + b.w) + cm3)) {
                 const int32_t slot = atomicAdd(&L.nn[k], 1);
                 if (slot < kWaveNear) L.near[k * kWaveNear + slot] = -(j + 1);
             }
